@@ -1,0 +1,296 @@
+"""FP64 network oracle -- TEST INFRASTRUCTURE (tests, smoke check and the
+benchmark's CPU-baseline leg only; the product never calls this).
+
+The network is the trimmed U-Net of the paper (Sec. 4.5: one 3x3
+convolution per level, bilinear upsampling instead of transposed
+convolutions, a sigmoid-bounded visibility output since visibility lies in
+[0, 1], supplemental Sec. 3) in the variant measured here: 2x2 max-pool
+between encoder levels and skip merge by channel concatenation [skip, up].
+
+Everything is float64.  Features and weights arrive as float32 and are
+promoted exactly.  Operations follow their plain definitions:
+
+  conv3x3   y[p, o] = b[o] + sum_{ky,kx,i} w[o,ky,kx,i] * x[p + (ky-1, kx-1), i]
+            with zero padding outside the image (a library matmul sums over i
+            for each of the nine taps);
+  relu      max(x, 0);
+  maxpool   2x2 windows, stride 2;
+  upsample  bilinear x2 with half-pixel centres and clamp-to-edge:
+            source coordinate s = (y + 0.5) / 2 - 0.5, taps floor(s) and
+            floor(s) + 1 clamped to the image, weights (1 - frac, frac);
+  head      1x1 convolution to one channel, then sigmoid 1 / (1 + e^-x).
+
+Backward (used for the differentiation form): the exact adjoint of each
+step.  ReLU passes gradient where its input is > 0 (derivative 0 at 0);
+max-pool routes each window's gradient to the first maximum in the order
+(0,0), (0,1), (1,0), (1,1); the upsampling adjoint is the transpose of the
+interpolation (scatter-add with the same weights); concat splits channels.
+
+Low-precision emulation: the same forward with round-to-nearest-even to the
+storage type (bfloat16 or float16) applied exactly where the GPU stores a
+value in that type (features on load, 3x3 weights, every stored activation
+and the upsampled operand), accumulating in float64.  The 1x1 head keeps
+float32 weights and reads the unrounded last activation.
+"""
+import numpy as np
+
+
+# ------------------------------------------------------------- descriptor
+def stages(c_in, widths):
+    """[(name, C_out, k, C_in)] in flat-vector order E0.., B, D(L-2)..D0, H."""
+    L = len(widths)
+    out = []
+    for l in range(L - 1):
+        out.append((f"E{l}", widths[l], 3, c_in if l == 0 else widths[l - 1]))
+    out.append(("B", widths[L - 1], 3, widths[L - 2] if L > 1 else c_in))
+    for l in range(L - 2, -1, -1):
+        out.append((f"D{l}", widths[l], 3, widths[l] + widths[l + 1]))
+    out.append(("H", 1, 1, widths[0]))
+    return out
+
+
+def split_params(c_in, widths, flat):
+    """Flat float32 vector -> {stage: (w [Co,k,k,Ci] f64, b [Co] f64)}."""
+    flat = np.asarray(flat)
+    res, off = {}, 0
+    for name, co, k, ci in stages(c_in, widths):
+        nw = co * k * k * ci
+        w = flat[off:off + nw].astype(np.float64).reshape(co, k, k, ci)
+        off += nw
+        b = flat[off:off + co].astype(np.float64)
+        off += co
+        res[name] = (w, b)
+    if off != flat.size:
+        raise ValueError(f"parameter vector has {flat.size} entries, descriptor needs {off}")
+    return res
+
+
+def join_params(c_in, widths, grads):
+    parts = []
+    for name, co, k, ci in stages(c_in, widths):
+        gw, gb = grads[name]
+        parts.append(np.asarray(gw, np.float64).reshape(-1))
+        parts.append(np.asarray(gb, np.float64).reshape(-1))
+    return np.concatenate(parts)
+
+
+# -------------------------------------------------------------- operations
+def conv3x3(x, w, b):
+    n, h, wd, ci = x.shape
+    co = w.shape[0]
+    xp = np.zeros((n, h + 2, wd + 2, ci))
+    xp[:, 1:-1, 1:-1] = x
+    y = np.empty((n, h, wd, co))
+    y[...] = b
+    for ky in range(3):
+        for kx in range(3):
+            y += xp[:, ky:ky + h, kx:kx + wd, :] @ w[:, ky, kx, :].T
+    return y
+
+
+def conv3x3_backward(x, w, dy):
+    """Adjoint of conv3x3: (dx, dw, db)."""
+    n, h, wd, ci = x.shape
+    xp = np.zeros((n, h + 2, wd + 2, ci))
+    xp[:, 1:-1, 1:-1] = x
+    dxp = np.zeros_like(xp)
+    dw = np.zeros_like(w)
+    dy2 = dy.reshape(-1, dy.shape[-1])
+    for ky in range(3):
+        for kx in range(3):
+            xs = xp[:, ky:ky + h, kx:kx + wd, :].reshape(-1, ci)
+            dw[:, ky, kx, :] = dy2.T @ xs
+            dxp[:, ky:ky + h, kx:kx + wd, :] += dy @ w[:, ky, kx, :]
+    db = dy2.sum(axis=0)
+    return dxp[:, 1:-1, 1:-1], dw, db
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def maxpool2(x):
+    n, h, w, c = x.shape
+    return x.reshape(n, h // 2, 2, w // 2, 2, c).max(axis=(2, 4))
+
+
+def maxpool2_backward(x, dy):
+    n, h, w, c = x.shape
+    win = x.reshape(n, h // 2, 2, w // 2, 2, c).transpose(0, 1, 3, 2, 4, 5).reshape(n, h // 2, w // 2, 4, c)
+    arg = np.argmax(win, axis=3)          # first maximum in (0,0),(0,1),(1,0),(1,1) order
+    dwin = np.zeros_like(win)
+    np.put_along_axis(dwin, arg[:, :, :, None, :], dy[:, :, :, None, :], axis=3)
+    return dwin.reshape(n, h // 2, w // 2, 2, 2, c).transpose(0, 1, 3, 2, 4, 5).reshape(n, h, w, c)
+
+
+def _interp_taps(n_out, n_in):
+    y = np.arange(n_out, dtype=np.float64)
+    s = (y + 0.5) / 2.0 - 0.5
+    i0 = np.floor(s)
+    fr = s - i0
+    i0 = i0.astype(np.int64)
+    i1 = i0 + 1
+    return np.clip(i0, 0, n_in - 1), np.clip(i1, 0, n_in - 1), 1.0 - fr, fr
+
+
+def upsample2(x):
+    n, h, w, c = x.shape
+    r0, r1, rw0, rw1 = _interp_taps(2 * h, h)
+    c0, c1, cw0, cw1 = _interp_taps(2 * w, w)
+    t = x[:, r0] * rw0[None, :, None, None] + x[:, r1] * rw1[None, :, None, None]
+    return t[:, :, c0] * cw0[None, None, :, None] + t[:, :, c1] * cw1[None, None, :, None]
+
+
+def upsample2_backward(dy, h, w):
+    n, _, _, c = dy.shape
+    r0, r1, rw0, rw1 = _interp_taps(2 * h, h)
+    c0, c1, cw0, cw1 = _interp_taps(2 * w, w)
+    dt = np.zeros((n, 2 * h, w, c))
+    np.add.at(dt, (slice(None), slice(None), c0), dy * cw0[None, None, :, None])
+    np.add.at(dt, (slice(None), slice(None), c1), dy * cw1[None, None, :, None])
+    dx = np.zeros((n, h, w, c))
+    np.add.at(dx, (slice(None), r0), dt * rw0[None, :, None, None])
+    np.add.at(dx, (slice(None), r1), dt * rw1[None, :, None, None])
+    return dx
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+# ------------------------------------------------------------------ network
+def forward(c_in, widths, flat, feat, keep=True):
+    """feat [N,H,W,C_in] (float32 or float64) -> dict with 'logits', 'vis' and
+    every activation (pre-activation 'z_*', post-ReLU 'a_*', pooled 'p_*')."""
+    P = split_params(c_in, widths, flat)
+    L = len(widths)
+    x = np.asarray(feat, np.float64)
+    if x.ndim == 3:
+        x = x[None]
+    n, h, w, c = x.shape
+    if c != c_in or h % (1 << (L - 1)) or w % (1 << (L - 1)):
+        raise ValueError("feature shape does not fit the descriptor")
+    act = {"x": x}
+    cur = x
+    skips = []
+    for l in range(L - 1):
+        z = conv3x3(cur, *P[f"E{l}"])
+        a = relu(z)
+        act[f"z_E{l}"], act[f"a_E{l}"] = z, a
+        skips.append(a)
+        cur = maxpool2(a)
+        act[f"p_E{l}"] = cur
+    z = conv3x3(cur, *P["B"])
+    cur = relu(z)
+    act["z_B"], act["a_B"] = z, cur
+    for l in range(L - 2, -1, -1):
+        u = upsample2(cur)
+        cat = np.concatenate([skips[l], u], axis=-1)
+        z = conv3x3(cat, *P[f"D{l}"])
+        cur = relu(z)
+        act[f"up_D{l}"], act[f"z_D{l}"], act[f"a_D{l}"] = u, z, cur
+    wh, bh = P["H"]
+    logits = cur @ wh[0, 0, 0, :] + bh[0]
+    act["logits"] = logits
+    act["vis"] = sigmoid(logits)
+    if not keep:
+        return {"logits": act["logits"], "vis": act["vis"]}
+    return act
+
+
+def backward(c_in, widths, flat, feat, dvis):
+    """Gradients of sum(dvis * vis) w.r.t. the flat parameters and the features.
+
+    Returns (dflat float64 [n_params], dfeat float64 [N,H,W,C_in])."""
+    P = split_params(c_in, widths, flat)
+    L = len(widths)
+    act = forward(c_in, widths, flat, feat)
+    dvis = np.asarray(dvis, np.float64).reshape(act["vis"].shape)
+    vis = act["vis"]
+    g = dvis * vis * (1.0 - vis)                      # d logits
+    wh, bh = P["H"]
+    top = act["a_D0"] if L > 1 else act["a_B"]
+    grads = {"H": (np.einsum("nhw,nhwc->c", g, top).reshape(1, 1, 1, -1), np.array([g.sum()]))}
+    dcur = g[..., None] * wh[0, 0, 0, :][None, None, None, :]
+    dskip = [None] * (L - 1)
+    for l in range(0, L - 1):
+        zname = f"D{l}"
+        dz = dcur * (act[f"z_{zname}"] > 0)
+        cat = np.concatenate([act[f"a_E{l}"], act[f"up_{zname}"]], axis=-1)
+        dcat, dw, db = conv3x3_backward(cat, P[zname][0], dz)
+        grads[zname] = (dw, db)
+        cs = widths[l]
+        dskip[l] = dcat[..., :cs]
+        lower = act["a_B"] if l == L - 2 else act[f"a_D{l + 1}"]
+        dcur = upsample2_backward(dcat[..., cs:], lower.shape[1], lower.shape[2])
+    dz = dcur * (act["z_B"] > 0)
+    inp = act[f"p_E{L - 2}"] if L > 1 else act["x"]
+    dinp, dw, db = conv3x3_backward(inp, P["B"][0], dz)
+    grads["B"] = (dw, db)
+    for l in range(L - 2, -1, -1):
+        da = dskip[l] + maxpool2_backward(act[f"a_E{l}"], dinp)
+        dz = da * (act[f"z_E{l}"] > 0)
+        inp = act["x"] if l == 0 else act[f"p_E{l - 1}"]
+        dinp, dw, db = conv3x3_backward(inp, P[f"E{l}"][0], dz)
+        grads[f"E{l}"] = (dw, db)
+    return join_params(c_in, widths, grads), dinp
+
+
+# ------------------------------------------------------ low-precision model
+def round_bf16(x):
+    """Round to the nearest bfloat16 (ties to even), via float32."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    nan = np.isnan(f)
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def round_f16(x):
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def forward_lowp(c_in, widths, flat, feat, dtype):
+    """Forward with storage rounding emulated at the GPU's store points."""
+    rnd = {"bf16": round_bf16, "f16": round_f16}[dtype]
+    P = split_params(c_in, widths, flat)
+    Pq = {k: (rnd(w), b) for k, (w, b) in P.items()}
+    Pq["H"] = P["H"]
+    L = len(widths)
+    x = rnd(np.asarray(feat, np.float64))
+    if x.ndim == 3:
+        x = x[None]
+    cur = x
+    skips = []
+    for l in range(L - 1):
+        a = relu(conv3x3(cur, *Pq[f"E{l}"]))
+        skips.append(rnd(a))
+        cur = rnd(maxpool2(a))
+    cur = rnd(relu(conv3x3(cur, *Pq["B"])))
+    for l in range(L - 2, -1, -1):
+        u = rnd(upsample2(cur))
+        a = relu(conv3x3(np.concatenate([skips[l], u], axis=-1), *Pq[f"D{l}"]))
+        cur = a if l == 0 else rnd(a)
+    wh, bh = Pq["H"]
+    logits = cur @ wh[0, 0, 0, :] + bh[0]
+    return {"logits": logits, "vis": sigmoid(logits)}
+
+
+# ------------------------------------------------------------ closed forms
+def count_macs_params(c_in, widths, height, width):
+    """(MACs per frame, parameters) of the descriptor at a given resolution."""
+    macs = 0
+    for name, co, k, ci in stages(c_in, widths):
+        if name == "H":
+            lvl = 0
+        elif name == "B":
+            lvl = len(widths) - 1
+        else:
+            lvl = int(name[1:])
+        px = (height >> lvl) * (width >> lvl)
+        macs += px * co * k * k * ci
+    params = sum(co * k * k * ci + co for _, co, k, ci in stages(c_in, widths))
+    return macs, params
