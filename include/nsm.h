@@ -1,0 +1,188 @@
+/*
+ * nsm.h -- C ABI of the neural shadow-mapping hot path on MI355X (gfx950).
+ *
+ * The method (Datta et al., "Neural Shadow Mapping", SIGGRAPH 2022) takes the
+ * buffers of a vanilla rasterised shadow-mapping pipeline -- a G-buffer with
+ * view depth and normals, a single light-view depth map, the receiver's
+ * depth towards the emitter and the emitter size -- composes a few
+ * screen-space feature channels from them (Sec. 3.1, 3.2) and runs a compact
+ * U-Net (Sec. 4.5) that outputs per-pixel shadow visibility in [0, 1].
+ *
+ * Three calls make up the path:
+ *   nsm_build_features  light-view z-buffer, camera G-buffer, feature gather
+ *   nsm_forward         U-Net inference (FP32, or BF16/FP16 on MFMA)
+ *   nsm_backward        gradient of the visibility w.r.t. the weights and
+ *                       the features (the differentiation form; FP32)
+ *
+ * Conventions shared by every call:
+ *   - Every tensor argument is a device pointer owned by the caller unless
+ *     marked "host".  The library never allocates or frees inside these
+ *     calls; scratch memory is the caller's `workspace`, sized by the
+ *     matching *_workspace_bytes query.  The one allocation the library
+ *     makes is the context's packed weight copy, in nsm_set_weights.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *     the null stream).  Inputs must stay valid until the stream has run.
+ *   - All arguments are validated before anything is launched; a non-OK
+ *     status means nothing was enqueued.  Faults inside kernels surface at
+ *     the caller's next synchronisation.  No C++ exception crosses the ABI.
+ *   - Images are row-major with row 0 at the bottom (ndc y = -1) and the
+ *     column index growing with ndc x; tensors are NHWC.
+ *   - A context is not internally synchronised: use one per stream.
+ */
+#ifndef NSM_H
+#define NSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSM_ABI_VERSION 1
+
+typedef enum {
+    NSM_OK = 0,
+    NSM_E_INVALID_ARG = 1,  /* null pointer, negative size, bad enum value      */
+    NSM_E_SHAPE = 2,        /* H or W not divisible by 2^(levels-1), size limits */
+    NSM_E_UNSUPPORTED = 3,  /* network or dtype this build has no kernels for    */
+    NSM_E_WORKSPACE = 4,    /* workspace missing or smaller than required        */
+    NSM_E_NO_WEIGHTS = 5,   /* nsm_set_weights has not been called               */
+    NSM_E_DEVICE = 6,       /* no HIP device, or a HIP runtime call failed       */
+    NSM_E_LAUNCH = 7        /* a kernel launch was rejected                      */
+} nsm_status;
+
+typedef enum { NSM_F32 = 0, NSM_BF16 = 1, NSM_F16 = 2 } nsm_dtype;
+
+/* Feature sets (channel order, NHWC, float32):
+ *   HARD6: [d/f_C, n.x, n.y, n.z, (z - z_f)/f_L, z/f_L]
+ *   SOFT8: HARD6 + [r_e/0.2, z_blk/f_L]
+ * d: view depth along the camera axis; n: face normal turned towards the
+ * camera; z: light-view linear depth stored in the shadow map at the
+ * receiver's texel; z_f: the receiver's own light-view linear depth; r_e:
+ * emitter radius; z_blk: mean linear depth of the 7x7 map texels in front
+ * of the receiver (z_f when there are none).  Background pixels are 0. */
+typedef enum { NSM_FEAT_HARD6 = 0, NSM_FEAT_SOFT8 = 1 } nsm_feature_set;
+
+typedef struct nsm_ctx nsm_ctx;
+
+/* U-Net descriptor: `levels` resolution levels with channel widths
+ * widths[0..levels-1].  Stages, in execution order: encoder 3x3 conv + ReLU
+ * + 2x2 max-pool for levels 0..L-2, bottleneck 3x3 conv + ReLU at level
+ * L-1, decoder bilinear x2 upsample, concat [skip, up], 3x3 conv + ReLU for
+ * levels L-2..0, then a 1x1 head to one channel and a sigmoid (one 3x3 conv
+ * per level and bilinear upsampling follow Sec. 4.5).
+ * Supported: c_in in {6, 8}; widths {8, 16} (levels 2) or {16, 32, 64}
+ * (levels 3). */
+typedef struct nsm_net_desc {
+    int32_t c_in;
+    int32_t levels;
+    int32_t widths[4];
+} nsm_net_desc;
+
+/* Per-frame light and camera (host struct, float32).  Matrices are
+ * row-major world -> clip with depth range [0, 1]; w_clip is the depth along
+ * the view axis.  The camera basis and tangents define the pixel-centre
+ * rays used to place each receiver on its triangle's plane. */
+typedef struct nsm_frame_params {
+    float m_light[16];
+    float light_pos[3];
+    float light_radius;         /* r_e; 0 for a point light               */
+    float light_near;
+    float light_far;            /* f_L                                    */
+    float light_tan_half_fov;   /* square light frustum                   */
+    int32_t sm_size;            /* S: the shadow map is S x S             */
+    float m_cam[16];
+    float cam_pos[3];
+    float cam_fwd[3];
+    float cam_right[3];
+    float cam_up[3];
+    float cam_tan_half_x;
+    float cam_tan_half_y;
+    float cam_near;
+    float cam_far;              /* f_C                                    */
+} nsm_frame_params;
+
+/* Library metadata. */
+int nsm_abi_version(void);
+const char *nsm_status_str(int status);
+
+/* ------------------------------------------------------------ features
+ * nsm_build_features -- one frame's network input from raw geometry
+ * (paper Sec. 3.1: "a G-buffer pass followed by a shadow mapping pass").
+ *
+ *   tris        [n_tris][3][3] float32, world-space vertices.
+ *   tri_normals [n_tris][3] float32 unit face normals.
+ *   fp          host; light and camera for this frame.
+ *   h, w        screen size (1..8192 each).
+ *   fs          feature set (HARD6 or SOFT8).
+ *   gbuf_in     [h][w] uint64 camera key buffer to use as the G-buffer, or
+ *               NULL to rasterise it from `tris` with fp->m_cam.
+ *   gbuf_out    [h][w] uint64; where the camera raster writes when gbuf_in
+ *               is NULL (NULL = keep it in the workspace).  Key =
+ *               depth_bits << 32 | triangle id, all ones where empty.
+ *   sm_out      [S][S] uint32 light-view depth bits (float32 ndc depth in
+ *               [0, 1], +inf bits where empty).
+ *   feat_out    [h][w][C] float32, C = 6 (HARD6) or 8 (SOFT8).
+ *   mask_out    [h][w] uint8 hard depth-test result (1 = shadowed), or NULL.
+ * The rasteriser and the gather are deterministic: repeated calls give
+ * identical bits.  Triangles with a vertex at w_clip <= 1e-6 or beyond the
+ * guard band [-8, 9] x the target size are skipped. */
+nsm_status nsm_features_workspace_bytes(int n_tris, int h, int w, int sm_size, size_t *bytes);
+nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n_tris,
+                              const nsm_frame_params *fp, int h, int w, nsm_feature_set fs,
+                              const uint64_t *gbuf_in, uint64_t *gbuf_out, uint32_t *sm_out,
+                              float *feat_out, uint8_t *mask_out, void *workspace,
+                              size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- network
+ * nsm_create -- a context for one network descriptor and compute dtype.
+ * Host only (no device call).  NSM_F32 runs the FP32 network; NSM_BF16 and
+ * NSM_F16 run the precision form (activations and 3x3 weights stored in
+ * that type, MFMA products accumulated in float32; the paper quantises its
+ * network to half precision, Sec. 4.5).  Inputs and outputs of every call
+ * stay float32. */
+nsm_status nsm_create(const nsm_net_desc *desc, nsm_dtype dtype, nsm_ctx **out);
+nsm_status nsm_destroy(nsm_ctx *ctx);
+
+/* Number of float32 entries in the flat parameter vector: stages in
+ * execution order E0..E(L-2), B, D(L-2)..D0, H; each stage's weights in
+ * OHWI order [C_out][k][k][C_in] followed by its biases [C_out]. */
+nsm_status nsm_param_count(const nsm_ctx *ctx, size_t *n);
+
+/* Copies (and converts / repacks) the flat float32 parameter vector `w`
+ * (device pointer, n entries) into the context.  Allocates the context's
+ * device copy on first use.  The caller may free `w` once the stream has
+ * run this call. */
+nsm_status nsm_set_weights(nsm_ctx *ctx, const float *w, size_t n, void *stream);
+
+/* Workspace bytes for nsm_forward (training = 0) or nsm_backward
+ * (training = 1) on n frames of h x w. */
+nsm_status nsm_workspace_bytes(const nsm_ctx *ctx, int n, int h, int w, int training,
+                               size_t *bytes);
+
+/* nsm_forward -- visibility for n frames.
+ *   feat       [n][h][w][c_in] float32.
+ *   vis_out    [n][h][w] float32 in (0, 1).
+ *   logits_out [n][h][w] float32 pre-sigmoid values, or NULL.
+ * h and w must be divisible by 2^(levels-1). */
+nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
+                       float *logits_out, void *workspace, size_t ws_bytes, void *stream);
+
+/* nsm_backward -- gradient of sum(dvis * vis) (FP32 contexts only).
+ * Recomputes the forward activations into the workspace, then applies the
+ * adjoint of every stage.
+ *   dvis       [n][h][w] float32 upstream gradient.
+ *   dw_out     [n_params] float32 in the flat parameter order; overwritten,
+ *              or added to when accumulate != 0.
+ *   dfeat_out  [n][h][w][c_in] float32 gradient w.r.t. the features, or NULL.
+ * The weight gradients are reduced in a fixed order (no float atomics), so
+ * results are bitwise reproducible. */
+nsm_status nsm_backward(nsm_ctx *ctx, const float *feat, const float *dvis, int n, int h, int w,
+                        float *dw_out, int accumulate, float *dfeat_out, void *workspace,
+                        size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSM_H */

@@ -1,0 +1,196 @@
+"""ctypes binding of ``libnsm.so`` with the C-ABI's names.
+
+Argument marshalling only: tensors are passed as raw device pointers and
+every step of the path runs in the library's HIP kernels.  There is no
+fallback: if the library has not been built the import of any entry point
+raises.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libnsm.so")
+
+NSM_OK = 0
+STATUS_NAMES = {0: "NSM_OK", 1: "NSM_E_INVALID_ARG", 2: "NSM_E_SHAPE", 3: "NSM_E_UNSUPPORTED",
+                4: "NSM_E_WORKSPACE", 5: "NSM_E_NO_WEIGHTS", 6: "NSM_E_DEVICE", 7: "NSM_E_LAUNCH"}
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+FEATURE_SETS = {"hard6": 0, "soft8": 1}
+
+EXPORTS = [
+    "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
+    "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
+    "nsm_forward", "nsm_backward",
+]
+
+
+class NsmError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+
+
+class NetDesc(ctypes.Structure):
+    _fields_ = [("c_in", ctypes.c_int32), ("levels", ctypes.c_int32), ("widths", ctypes.c_int32 * 4)]
+
+
+class FrameParams(ctypes.Structure):
+    _fields_ = [
+        ("m_light", ctypes.c_float * 16), ("light_pos", ctypes.c_float * 3),
+        ("light_radius", ctypes.c_float), ("light_near", ctypes.c_float),
+        ("light_far", ctypes.c_float), ("light_tan_half_fov", ctypes.c_float),
+        ("sm_size", ctypes.c_int32), ("m_cam", ctypes.c_float * 16),
+        ("cam_pos", ctypes.c_float * 3), ("cam_fwd", ctypes.c_float * 3),
+        ("cam_right", ctypes.c_float * 3), ("cam_up", ctypes.c_float * 3),
+        ("cam_tan_half_x", ctypes.c_float), ("cam_tan_half_y", ctypes.c_float),
+        ("cam_near", ctypes.c_float), ("cam_far", ctypes.c_float),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libnsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    psz = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "nsm_abi_version": ([], i32),
+        "nsm_status_str": ([i32], ctypes.c_char_p),
+        "nsm_features_workspace_bytes": ([i32, i32, i32, i32, psz], i32),
+        "nsm_build_features": ([vp, vp, i32, ctypes.POINTER(FrameParams), i32, i32, i32, vp, vp, vp,
+                                vp, vp, vp, sz, vp], i32),
+        "nsm_create": ([ctypes.POINTER(NetDesc), i32, ctypes.POINTER(vp)], i32),
+        "nsm_destroy": ([vp], i32),
+        "nsm_param_count": ([vp, psz], i32),
+        "nsm_set_weights": ([vp, vp, sz, vp], i32),
+        "nsm_workspace_bytes": ([vp, i32, i32, i32, i32, psz], i32),
+        "nsm_forward": ([vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
+        "nsm_backward": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    """Device pointer of a tensor (or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _check(status, where):
+    if status != NSM_OK:
+        raise NsmError(status, where)
+
+
+# ------------------------------------------------------------ entry points
+def nsm_abi_version():
+    return load().nsm_abi_version()
+
+
+def nsm_status_str(status):
+    return load().nsm_status_str(int(status)).decode()
+
+
+def nsm_features_workspace_bytes(n_tris, h, w, sm_size):
+    out = ctypes.c_size_t()
+    _check(load().nsm_features_workspace_bytes(n_tris, h, w, sm_size, ctypes.byref(out)),
+           "nsm_features_workspace_bytes")
+    return out.value
+
+
+def frame_params(fr):
+    """ctypes FrameParams from an nsm_synth FrameParams."""
+    p = FrameParams()
+    p.m_light[:] = [float(v) for v in fr.m_light.reshape(-1)]
+    p.light_pos[:] = [float(v) for v in fr.light_pos]
+    p.light_radius = fr.light_radius
+    p.light_near = fr.light_near
+    p.light_far = fr.light_far
+    p.light_tan_half_fov = fr.light_tan_half_fov
+    p.sm_size = fr.sm_size
+    p.m_cam[:] = [float(v) for v in fr.m_cam.reshape(-1)]
+    p.cam_pos[:] = [float(v) for v in fr.cam_pos]
+    p.cam_fwd[:] = [float(v) for v in fr.cam_fwd]
+    p.cam_right[:] = [float(v) for v in fr.cam_right]
+    p.cam_up[:] = [float(v) for v in fr.cam_up]
+    p.cam_tan_half_x = fr.cam_tan_half_x
+    p.cam_tan_half_y = fr.cam_tan_half_y
+    p.cam_near = fr.cam_near
+    p.cam_far = fr.cam_far
+    return p
+
+
+def nsm_build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_out, sm_out, feat_out,
+                       mask_out, workspace, ws_bytes, stream=None):
+    if not isinstance(fp, FrameParams):
+        fp = frame_params(fp)
+    fs = FEATURE_SETS.get(fs, fs)
+    _check(load().nsm_build_features(_ptr(tris), _ptr(tri_normals), n_tris, ctypes.byref(fp), h, w,
+                                     fs, _ptr(gbuf_in), _ptr(gbuf_out), _ptr(sm_out), _ptr(feat_out),
+                                     _ptr(mask_out), _ptr(workspace), ws_bytes, _stream(stream)),
+           "nsm_build_features")
+
+
+def nsm_create(c_in, widths, dtype="f32"):
+    d = NetDesc()
+    d.c_in = c_in
+    d.levels = len(widths)
+    for i, v in enumerate(widths):
+        d.widths[i] = v
+    h = ctypes.c_void_p()
+    _check(load().nsm_create(ctypes.byref(d), DTYPES.get(dtype, dtype), ctypes.byref(h)), "nsm_create")
+    return h.value
+
+
+def nsm_destroy(ctx):
+    _check(load().nsm_destroy(ctx), "nsm_destroy")
+
+
+def nsm_param_count(ctx):
+    out = ctypes.c_size_t()
+    _check(load().nsm_param_count(ctx, ctypes.byref(out)), "nsm_param_count")
+    return out.value
+
+
+def nsm_set_weights(ctx, w, n, stream=None):
+    _check(load().nsm_set_weights(ctx, _ptr(w), n, _stream(stream)), "nsm_set_weights")
+
+
+def nsm_workspace_bytes(ctx, n, h, w, training=0):
+    out = ctypes.c_size_t()
+    _check(load().nsm_workspace_bytes(ctx, n, h, w, int(training), ctypes.byref(out)),
+           "nsm_workspace_bytes")
+    return out.value
+
+
+def nsm_forward(ctx, feat, n, h, w, vis_out, logits_out, workspace, ws_bytes, stream=None):
+    _check(load().nsm_forward(ctx, _ptr(feat), n, h, w, _ptr(vis_out), _ptr(logits_out),
+                              _ptr(workspace), ws_bytes, _stream(stream)), "nsm_forward")
+
+
+def nsm_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, workspace, ws_bytes,
+                 stream=None):
+    _check(load().nsm_backward(ctx, _ptr(feat), _ptr(dvis), n, h, w, _ptr(dw_out), int(accumulate),
+                               _ptr(dfeat_out), _ptr(workspace), ws_bytes, _stream(stream)),
+           "nsm_backward")

@@ -1,0 +1,134 @@
+"""Convenience wrappers over the C ABI (marshalling and buffer management only).
+
+``FeatureBuilder`` keeps a scene's triangles on the device and calls
+``nsm_build_features``; ``ShadowNet`` owns a network context and its
+workspace and calls ``nsm_forward`` / ``nsm_backward``; ``NSMForward`` is the
+differentiation form as a ``torch.autograd.Function``.  PyTorch only
+provides device memory and the current stream.
+"""
+import torch
+
+from . import _lib
+
+
+def _dev(device):
+    return torch.device(device if device is not None else "cuda")
+
+
+class FeatureBuilder:
+    """Builds one frame's network input from a triangle scene on the GPU."""
+
+    def __init__(self, scene, device=None):
+        dev = _dev(device)
+        self.device = dev
+        self.tris = torch.from_numpy(scene.tris).to(dev).contiguous()
+        self.normals = torch.from_numpy(scene.normals).to(dev).contiguous()
+        self.n_tris = int(scene.tris.shape[0])
+        self._ws = None
+
+    def workspace(self, h, w, sm_size):
+        need = _lib.nsm_features_workspace_bytes(self.n_tris, h, w, sm_size)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def __call__(self, fr, soft=False, out=None, stream=None):
+        """Returns dict(feat [H,W,C] f32, mask [H,W] u8, sm [S,S] i32 bits, gbuf [H,W] i64 keys)."""
+        h, w, S = fr.height, fr.width, fr.sm_size
+        C = 8 if soft else 6
+        if out is None:
+            out = {
+                "feat": torch.empty((h, w, C), dtype=torch.float32, device=self.device),
+                "mask": torch.empty((h, w), dtype=torch.uint8, device=self.device),
+                "sm": torch.empty((S, S), dtype=torch.int32, device=self.device),
+                "gbuf": torch.empty((h, w), dtype=torch.int64, device=self.device),
+            }
+        ws = self.workspace(h, w, S)
+        _lib.nsm_build_features(self.tris, self.normals, self.n_tris, fr, h, w,
+                                "soft8" if soft else "hard6", None, out["gbuf"], out["sm"],
+                                out["feat"], out["mask"], ws, ws.numel(), stream)
+        return out
+
+
+class ShadowNet:
+    """A network context (descriptor + dtype) with its device weights."""
+
+    def __init__(self, c_in, widths, dtype="f32", device=None):
+        self.device = _dev(device)
+        self.c_in, self.widths, self.dtype = int(c_in), tuple(int(v) for v in widths), dtype
+        self.ctx = _lib.nsm_create(self.c_in, self.widths, dtype)
+        self.n_params = _lib.nsm_param_count(self.ctx)
+        self._ws = None
+        self._w = None
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                _lib.nsm_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    def set_weights(self, flat, stream=None):
+        flat = torch.as_tensor(flat, dtype=torch.float32).to(self.device).contiguous()
+        if flat.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {flat.numel()}")
+        self._w = flat          # keep alive until the stream has copied it
+        _lib.nsm_set_weights(self.ctx, flat, self.n_params, stream)
+
+    def workspace(self, n, h, w, training=False):
+        need = _lib.nsm_workspace_bytes(self.ctx, n, h, w, int(training))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def forward(self, feat, logits=False, vis_out=None, logits_out=None, stream=None):
+        if feat.dim() == 3:
+            feat = feat.unsqueeze(0)
+        n, h, w, c = feat.shape
+        if c != self.c_in or feat.dtype != torch.float32 or not feat.is_contiguous():
+            raise ValueError("features must be contiguous float32 [N,H,W,c_in]")
+        vis = vis_out if vis_out is not None else torch.empty((n, h, w), dtype=torch.float32,
+                                                              device=feat.device)
+        lg = logits_out
+        if logits and lg is None:
+            lg = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
+        ws = self.workspace(n, h, w)
+        _lib.nsm_forward(self.ctx, feat, n, h, w, vis, lg, ws, ws.numel(), stream)
+        return (vis, lg) if logits else vis
+
+    def backward(self, feat, dvis, dw_out=None, accumulate=False, want_dfeat=True, stream=None):
+        if feat.dim() == 3:
+            feat = feat.unsqueeze(0)
+        n, h, w, c = feat.shape
+        dvis = dvis.reshape(n, h, w).contiguous()
+        dw = dw_out if dw_out is not None else torch.empty(self.n_params, dtype=torch.float32,
+                                                           device=feat.device)
+        df = torch.empty_like(feat) if want_dfeat else None
+        ws = self.workspace(n, h, w, training=True)
+        _lib.nsm_backward(self.ctx, feat, dvis, n, h, w, dw, int(accumulate), df, ws, ws.numel(),
+                          stream)
+        return dw, df
+
+
+class NSMForward(torch.autograd.Function):
+    """vis = net(feat; weights) with the hand-written backward kernels.
+
+    Saves only the features; the backward recomputes the activations."""
+
+    @staticmethod
+    def forward(ctx, feat, weights, net):
+        net.set_weights(weights.detach())
+        ctx.net = net
+        ctx.save_for_backward(feat, weights)
+        return net.forward(feat.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, dvis):
+        feat, weights = ctx.saved_tensors
+        net = ctx.net
+        net.set_weights(weights.detach())
+        dw, df = net.backward(feat.detach().contiguous(), dvis.contiguous(),
+                              want_dfeat=ctx.needs_input_grad[0])
+        return (df if ctx.needs_input_grad[0] else None), dw, None

@@ -1,0 +1,79 @@
+// Internal launch interface between the C-ABI layer and the kernel files.
+// Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/nsm.h"
+
+namespace nsm {
+
+// ------------------------------------------------------------ rasteriser
+// 64-byte per-triangle record written by the setup kernel.
+struct alignas(16) TriSetup {
+    int32_t x[3], y[3];   // 24.8 fixed-point screen coordinates, CCW order
+    float z[3];           // ndc depth per vertex
+    int32_t tx0, ty0;     // first 8x8 tile of the texel bounding box
+    int32_t ntx;          // tiles per bounding-box row (count = ntx * nty)
+    int64_t area;         // doubled signed area (> 0 after reordering)
+    int32_t pad;
+};
+static_assert(sizeof(TriSetup) == 64, "TriSetup must stay 64 bytes");
+
+struct Mat4 { float m[16]; };
+
+// Workspace needed by one raster pass over n_tris triangles.
+size_t raster_workspace_bytes(int n_tris);
+// Clear `out` (w*h texels of 4 or 8 bytes) and rasterise; key64 selects the
+// camera key (depth bits << 32 | id) instead of plain depth bits.
+hipError_t raster(const float* tris, int n_tris, const Mat4& m, int w, int h, bool key64,
+                  void* out, void* ws, hipStream_t s);
+
+struct GatherParams {
+    Mat4 ml;
+    float L[3], r_e, nl, fl, tanl;
+    int S;
+    float E[3], fwd[3], right[3], up[3];
+    float tanx, tany, fc;
+};
+hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
+                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, bool soft, float* feat,
+                  uint8_t* mask, hipStream_t s);
+
+// --------------------------------------------------------------- network
+enum class Dt { F32 = 0, BF16 = 1, F16 = 2 };
+
+// One 3x3 conv stage as the kernels see it.
+struct ConvStage {
+    int cs;      // channels read from the same-resolution input (skip / plain input)
+    int cu;      // channels produced by bilinear x2 upsampling of the lower level (0 if none)
+    int co;      // output channels
+};
+
+// Packed-weight bytes of one stage for a dtype (layout private to conv.hip).
+size_t packed_weight_bytes(const ConvStage& st, Dt dt);
+// Repack OHWI float32 weights of one stage into the kernel layout.
+hipError_t pack_weights(const ConvStage& st, Dt dt, const float* w_ohwi, void* packed,
+                        hipStream_t s);
+
+enum class OutMode { Store = 0, Pool = 1, Head = 2 };
+
+struct ConvArgs {
+    const void* in;      // plain input [n][h][w][cs] (float32 when in_f32, else the stage dtype)
+    const void* low;     // lower level [n][h/2][w/2][cu] for upsampling (stage dtype)
+    const void* wpk;     // packed weights
+    const float* bias;   // [co]
+    void* out;           // [n][h][w][co] stage dtype (Store/Pool), or NULL for Head
+    void* pooled;        // [n][h/2][w/2][co] (Pool)
+    const float* head_w; // [co] + bias at head_w[co] (Head)
+    float* vis;          // [n][h][w] (Head)
+    float* logits;       // [n][h][w] or NULL (Head)
+    float* act_out;      // [n][h][w][co] float32 post-ReLU copy or NULL (Head, training)
+    int n, h, w;
+    bool in_f32;
+};
+hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs& a, hipStream_t s);
+bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32);
+
+}  // namespace nsm

@@ -1,0 +1,104 @@
+"""C-ABI contract checks that need no GPU.
+
+The library must load, export every function ``include/nsm.h`` declares, and
+reject bad arguments with the documented status before touching the device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2301_05262_amd as nsm
+from paper_2301_05262_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "nsm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_abi_version_and_status_strings(lib):
+    assert nsm.nsm_abi_version() == 1
+    for s in range(8):
+        assert nsm.nsm_status_str(s) != "unknown status"
+    assert nsm.nsm_status_str(99) == "unknown status"
+
+
+def test_struct_layouts_match_header():
+    # nsm_net_desc: 6 int32; nsm_frame_params: 16+3+1+3+1 + 16+3+3+3+3+4 scalars of 4 bytes
+    assert ctypes.sizeof(_lib.NetDesc) == 24
+    assert ctypes.sizeof(_lib.FrameParams) == 4 * (16 + 3 + 1 + 3 + 1 + 16 + 3 + 3 + 3 + 3 + 4)
+
+
+def test_create_validation_and_param_counts():
+    ctx = nsm.nsm_create(6, (16, 32, 64), "f32")
+    try:
+        assert nsm.nsm_param_count(ctx) == 58641
+        assert nsm.nsm_workspace_bytes(ctx, 1, 1080, 1920) > 0
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_workspace_bytes(ctx, 1, 1082, 1920)      # not divisible by 4
+        assert e.value.status == 2
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_workspace_bytes(ctx, 0, 64, 64)
+        assert e.value.status == 2
+        # forward before set_weights: NSM_E_NO_WEIGHTS, before any device call
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_forward(ctx, 1024, 1, 64, 64, 2048, None, 4096, 1 << 30, 0)
+        assert e.value.status == 5
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_forward(ctx, None, 1, 64, 64, 2048, None, 4096, 1 << 30, 0)
+        assert e.value.status == 1
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_set_weights(ctx, 1024, 17, 0)              # wrong count
+        assert e.value.status == 1
+    finally:
+        nsm.nsm_destroy(ctx)
+    ctx = nsm.nsm_create(6, (8, 16), "bf16")
+    assert nsm.nsm_param_count(ctx) == 3353
+    nsm.nsm_destroy(ctx)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_create(6, (16, 32, 48), "f32")                  # no kernels for this width set
+    assert e.value.status == 3
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_create(6, (16, 32, 64), 7)
+    assert e.value.status == 1
+
+
+def test_features_validation():
+    import nsm_synth as S
+    sc, fr = S.workload_frame("tiny_64", 0)
+    need = nsm.nsm_features_workspace_bytes(sc.n_tris, 64, 64, 128)
+    assert need >= 64 * 64 * 8
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_features_workspace_bytes(10, 0, 64, 128)
+    assert e.value.status == 2
+    fp = _lib.frame_params(fr)
+    args = dict(tris=1024, tri_normals=2048, n_tris=sc.n_tris, fp=fp, h=64, w=64, fs="hard6",
+                gbuf_in=None, gbuf_out=None, sm_out=4096, feat_out=8192, mask_out=None,
+                workspace=16384, ws_bytes=need, stream=0)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_build_features(**{**args, "ws_bytes": need - 1})
+    assert e.value.status == 4
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_build_features(**{**args, "feat_out": None})
+    assert e.value.status == 1
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_build_features(**{**args, "fs": 5})
+    assert e.value.status == 1

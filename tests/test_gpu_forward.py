@@ -1,0 +1,124 @@
+"""GPU parity of nsm_forward against the FP64 network oracle.
+
+FP32: max |gpu - oracle| <= 1e-5 * max |oracle| on logits and on visibility
+(norm-wise, per tensor).  BF16 / FP16 (precision form): max |vis - vis_fp64|
+<= 2e-2 over all pixels, reported beside the storage-rounding emulation.
+Shapes cover several tiles with ragged tails, batches, the tiny 64x64 U2
+workload, the 1080p U3 workload bench.py times, and the soft 8-channel net.
+"""
+import numpy as np
+import pytest
+import torch
+
+import nsm_synth as S
+import oracle
+from oracle import net as onet
+
+pytestmark = pytest.mark.gpu
+
+FP32_REL = 1e-5
+LOWP_ABS = 2e-2
+
+
+def _net(desc, dtype, flat):
+    from paper_2301_05262_amd.api import ShadowNet
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    m = ShadowNet(desc.c_in, desc.widths, dtype)
+    m.set_weights(torch.from_numpy(flat))
+    return m
+
+
+def _run(m, feat):
+    f = torch.from_numpy(np.ascontiguousarray(feat, np.float32)).cuda()
+    vis, lg = m.forward(f, logits=True)
+    torch.cuda.synchronize()
+    return vis.cpu().numpy().astype(np.float64), lg.cpu().numpy().astype(np.float64)
+
+
+def _check_fp32(vis, lg, ref, tag):
+    e_l = np.abs(lg - ref["logits"]).max() / np.abs(ref["logits"]).max()
+    e_v = np.abs(vis - ref["vis"]).max() / np.abs(ref["vis"]).max()
+    print(f"[{tag}] fp32 norm-wise rel err: logits {e_l:.3e} vis {e_v:.3e}", flush=True)
+    assert e_l <= FP32_REL and e_v <= FP32_REL
+
+
+def _rand_feat(n, h, w, c, seed):
+    return S.SplitMix64(seed).uniforms(n * h * w * c, -1, 1).reshape(n, h, w, c).astype(np.float32)
+
+
+@pytest.mark.parametrize("desc,shape", [(S.U2, (2, 64, 64)), (S.U3, (3, 72, 200)),
+                                        (S.U3_SOFT, (1, 40, 96)), (S.U3, (1, 4, 4))])
+def test_fp32_random_features(desc, shape):
+    n, h, w = shape
+    flat = S.he_weights(desc, 11, bias_scale=0.1)
+    feat = _rand_feat(n, h, w, desc.c_in, 12)
+    ref = onet.forward(desc.c_in, desc.widths, flat, feat, keep=False)
+    vis, lg = _run(_net(desc, "f32", flat), feat)
+    _check_fp32(vis, lg, ref, f"{desc.widths}/{shape}")
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("desc,shape", [(S.U2, (2, 64, 64)), (S.U3, (2, 72, 200))])
+def test_lowp_random_features(desc, shape, dtype):
+    n, h, w = shape
+    flat = S.he_weights(desc, 13, bias_scale=0.1)
+    feat = _rand_feat(n, h, w, desc.c_in, 14)
+    ref = onet.forward(desc.c_in, desc.widths, flat, feat, keep=False)
+    emu = onet.forward_lowp(desc.c_in, desc.widths, flat, feat, dtype)
+    vis, _ = _run(_net(desc, dtype, flat), feat)
+    e64 = np.abs(vis - ref["vis"]).max()
+    eemu = np.abs(vis - emu["vis"]).max()
+    floor = np.abs(emu["vis"] - ref["vis"]).max()
+    print(f"[{desc.widths}/{dtype}] |vis-fp64| {e64:.3e}  |vis-emulated| {eemu:.3e}  emulated floor {floor:.3e}",
+          flush=True)
+    assert e64 <= LOWP_ABS and eemu <= LOWP_ABS
+
+
+def test_tiny_workload_with_oracle_features():
+    desc = S.U2
+    flat = S.he_weights(desc, 0)
+    feats = []
+    for seed in (0, 1):
+        sc, fr = S.workload_frame("tiny_64", seed)
+        feats.append(oracle.build_features(sc, fr)["feat"])
+    feat = np.stack(feats)
+    ref = onet.forward(desc.c_in, desc.widths, flat, feat, keep=False)
+    vis, lg = _run(_net(desc, "f32", flat), feat)
+    _check_fp32(vis, lg, ref, "tiny_64")
+
+
+@pytest.fixture(scope="module")
+def hd_case():
+    sc, fr = S.workload_frame("hard_1080p", 0)
+    feat = oracle.build_features(sc, fr)["feat"][None]
+    flat = S.he_weights(S.U3, 0)
+    ref = onet.forward(6, S.U3.widths, flat, feat, keep=False)
+    return feat, flat, ref
+
+
+def test_fp32_1080p_full_frame(hd_case):
+    feat, flat, ref = hd_case
+    m = _net(S.U3, "f32", flat)
+    vis, lg = _run(m, feat)
+    _check_fp32(vis, lg, ref, "1080p")
+    vis2, lg2 = _run(m, feat)
+    np.testing.assert_array_equal(vis, vis2)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_lowp_1080p_full_frame(hd_case, dtype):
+    feat, flat, ref = hd_case
+    vis, _ = _run(_net(S.U3, dtype, flat), feat)
+    err = np.abs(vis - ref["vis"])
+    print(f"[1080p/{dtype}] max {err.max():.3e} mean {err.mean():.3e} p99 {np.quantile(err, 0.99):.3e} "
+          f"mse {np.mean(err ** 2):.3e}", flush=True)
+    assert err.max() <= LOWP_ABS
+
+
+def test_soft_net_on_soft_features():
+    sc, frames = S.make_train_window(0, 2)
+    feat = oracle.build_features(sc, frames[0], soft=True)["feat"][None]
+    flat = S.he_weights(S.U3_SOFT, 1, bias_scale=0.1)
+    ref = onet.forward(8, S.U3_SOFT.widths, flat, feat, keep=False)
+    vis, lg = _run(_net(S.U3_SOFT, "f32", flat), feat)
+    _check_fp32(vis, lg, ref, "soft512")
