@@ -1,0 +1,212 @@
+"""Benchmark: ms/frame of 1080p neural shadow-map inference on one MI355X.
+
+One step = the whole inference path for one 1920x1080 frame of the
+19,632-triangle synthetic scene with a 2048^2 shadow map: light-view
+z-buffer, camera G-buffer, feature gather (HARD6) and the U-Net forward
+(U3: widths 16/32/64).  `value` is the BF16 form's ms/frame; the FP32 and
+FP16 forms are timed the same way and reported beside it, each with its
+visibility error against the FP64 oracle.
+
+Timing: W untimed warm-up steps, then K steps bracketed by
+torch.cuda.synchronize() with events on the launch stream (the library
+launches on torch's current stream).  A second, traced pass over K steps
+records HIP events around every kernel (on its launch stream) to get
+per-kernel durations for the roofline; the untraced pass gives `value`.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-sample frame|none]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms/frame 1080p shadow-net inference, BF16 vs FP32, at stated visibility error"
+HBM_PEAK = 8.0e12                         # B/s
+MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}   # dense FLOP/s
+WORKLOAD = "hard_1080p"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-sample", default="frame", choices=["frame", "none"])
+    ap.add_argument("--forms", default="bf16,f32,f16")
+    return ap.parse_args()
+
+
+def stage_costs(widths, c_in, h, w, dtype):
+    """Algorithmic FLOPs and HBM bytes per frame of each conv stage (fused:
+    every tensor written once and read once per consumer; weights included)."""
+    es = 4 if dtype == "f32" else 2
+    w0, w1, w2 = widths
+    L1, L2 = (h // 2) * (w // 2), (h // 4) * (w // 4)
+    L0 = h * w
+    out = {}
+
+    def add(key, px, cs, cu, co, in_bytes, out_bytes):
+        flops = 2.0 * px * co * 9 * (cs + cu)
+        wbytes = co * 9 * (cs + cu) * es + co * 4
+        out[key] = (flops, in_bytes + out_bytes + wbytes)
+
+    add(f"conv3x3 {c_in}+0->{w0} Pool", L0, c_in, 0, w0, L0 * c_in * 4, L0 * w0 * es + L1 * w0 * es)
+    add(f"conv3x3 {w0}+0->{w1} Pool", L1, w0, 0, w1, L1 * w0 * es, L1 * w1 * es + L2 * w1 * es)
+    add(f"conv3x3 {w1}+0->{w2} Store", L2, w1, 0, w2, L2 * w1 * es, L2 * w2 * es)
+    add(f"conv3x3 {w1}+{w2}->{w1} Store", L1, w1, w2, w1, L1 * w1 * es + L2 * w2 * es, L1 * w1 * es)
+    add(f"conv3x3 {w0}+{w1}->{w0} Head", L0, w0, w1, w0, L0 * w0 * es + L1 * w1 * es, L0 * 4)
+    k = f"conv3x3 {w0}+{w1}->{w0} Head"
+    fl, by = out[k]
+    out[k] = (fl + 2.0 * L0 * w0, by)          # the fused 1x1 head
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path has no multi-GPU "
+              "mode in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import nsm_synth as S
+    import paper_2301_05262_amd as nsm
+    from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    scene, fr = S.workload_frame(WORKLOAD, args.seed)
+    H, W = fr.height, fr.width
+    desc = S.U3
+    flat = S.he_weights(desc, args.seed)
+    fb = FeatureBuilder(scene, dev)
+    buf = fb(fr)
+    forms = [f for f in args.forms.split(",") if f]
+    nets = {}
+    for f in forms:
+        nets[f] = ShadowNet(desc.c_in, desc.widths, f, dev)
+        nets[f].set_weights(torch.from_numpy(flat))
+    feat = buf["feat"].unsqueeze(0)
+    vis = {f: torch.empty((1, H, W), dtype=torch.float32, device=dev) for f in forms}
+    torch.cuda.synchronize()
+
+    def step(f):
+        fb(fr, out=buf)
+        nets[f].forward(feat, vis_out=vis[f])
+
+    def net_only(f):
+        nets[f].forward(feat, vis_out=vis[f])
+
+    def timed(fn, f, k):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(k):
+            fn(f)
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / k
+
+    results = {}
+    for f in forms:
+        for _ in range(args.warmup):
+            step(f)
+        ms_step = timed(step, f, args.steps)
+        ms_net = timed(net_only, f, args.steps)
+        # traced pass: per-kernel durations
+        nsm.nsm_trace_read()
+        nsm.nsm_trace_enable(True)
+        for _ in range(args.steps):
+            step(f)
+        torch.cuda.synchronize()
+        recs = nsm.nsm_trace_read(1 << 16)
+        nsm.nsm_trace_enable(False)
+        per = {}
+        for name, ms in recs:
+            per.setdefault(name, []).append(ms)
+        kern = {k: {"avg_us": 1e3 * float(np.mean(v)), "launches": len(v)} for k, v in per.items()}
+        results[f] = {"ms_per_frame": ms_step, "network_ms": ms_net, "features_ms": ms_step - ms_net,
+                      "kernels": kern}
+        print(f"[bench] {f}: step {ms_step:.4f} ms  network {ms_net:.4f} ms", file=sys.stderr, flush=True)
+
+    # visibility error of each form against the FP64 oracle (and the CPU baseline timing)
+    cpu = None
+    if args.cpu_sample == "frame":
+        import oracle
+        from oracle import net as onet
+        t0 = time.perf_counter()
+        ofe = oracle.build_features(scene, fr)
+        ref = onet.forward(desc.c_in, desc.widths, flat, ofe["feat"][None], keep=False)
+        t1 = time.perf_counter()
+        threads = os.cpu_count() or 1
+        try:
+            import threadpoolctl
+            info = threadpoolctl.threadpool_info()
+            threads = max([threads if "OMP_NUM_THREADS" not in os.environ else int(os.environ["OMP_NUM_THREADS"])]
+                          + [int(i.get("num_threads", 1)) for i in info])
+        except Exception:
+            pass
+        cpu = {"value": 1e3 * (t1 - t0), "unit": "ms/frame", "cores": threads, "kind": "oracle",
+               "sample": "one full 1920x1080 frame: C rasteriser (2048^2 map + camera), C gather, "
+                         "numpy float64 U-Net forward"}
+        for f in forms:
+            v = vis[f].cpu().numpy()[0].astype(np.float64)
+            d = np.abs(v - ref["vis"][0])
+            results[f]["vis_err_vs_fp64"] = {"max_abs": float(d.max()), "mean_abs": float(d.mean()),
+                                             "norm_rel": float(d.max() / np.abs(ref["vis"]).max())}
+
+    # roofline of the dominant kernel of the headline (BF16) form
+    head = "bf16" if "bf16" in forms else forms[0]
+    costs = stage_costs(desc.widths, desc.c_in, H, W, head)
+    kern = results[head]["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["avg_us"])
+    base = dom.rsplit(" ", 1)[0]
+    roof = None
+    for f in forms:
+        c = stage_costs(desc.widths, desc.c_in, H, W, f)
+        for k, v in results[f]["kernels"].items():
+            b = k.rsplit(" ", 1)[0]
+            if b in c:
+                fl, by = c[b]
+                t = v["avg_us"] * 1e-6
+                v["gflop"] = fl / 1e9
+                v["mbytes"] = by / 1e6
+                v["tflops"] = fl / t / 1e12
+                v["gbps"] = by / t / 1e9
+                v["frac_mfma"] = fl / t / MFMA_PEAK[f]
+                v["frac_hbm"] = by / t / HBM_PEAK
+    if base in costs:
+        fl, by = costs[base]
+        t = kern[dom]["avg_us"] * 1e-6
+        ai = fl / by
+        if ai >= MFMA_PEAK[head] / HBM_PEAK:
+            roof = {"kernel": dom, "bound": "mfma", "achieved": fl / t / 1e12, "peak": MFMA_PEAK[head] / 1e12,
+                    "unit": "TFLOP/s", "frac": (fl / t) / MFMA_PEAK[head]}
+        else:
+            roof = {"kernel": dom, "bound": "hbm", "achieved": by / t / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": (by / t) / HBM_PEAK}
+        roof.update({"traffic": None, "avg_us": kern[dom]["avg_us"], "algorithmic_bytes": by,
+                     "algorithmic_flops": fl})
+    ms = results[head]["ms_per_frame"]
+    line = {
+        "metric": METRIC, "value": ms, "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": head, "data": "synthetic",
+        "config": {"workload": WORKLOAD, "width": W, "height": H, "sm_size": fr.sm_size,
+                   "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
+                   "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
+        "forms": results, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,18 @@ nsm_status nsm_backward(nsm_ctx *ctx, const float *feat, const float *dvis, int 
                         float *dw_out, int accumulate, float *dfeat_out, void *workspace,
                         size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------- diagnostics
+ * Per-kernel timing.  While enabled (process-wide), every kernel the
+ * library launches is bracketed by two hipEvents recorded on its launch
+ * stream, so the measured time is the kernel's own execution.
+ * nsm_trace_read waits for the recorded events, writes up to max_records
+ * entries (names: max_records x 64 chars, NUL-terminated; ms: durations)
+ * in launch order, stores the number of records consumed in *n_out and
+ * clears the list.  Tracing adds the event records between launches, so
+ * time whole calls with tracing off. */
+nsm_status nsm_trace_enable(int on);
+nsm_status nsm_trace_read(int max_records, char *names, float *ms, int *n_out);
+
 #ifdef __cplusplus
 }
 #endif

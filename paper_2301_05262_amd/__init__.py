@@ -22,6 +22,8 @@ from ._lib import (  # noqa: F401
     nsm_forward,
     nsm_backward,
     frame_params,
+    nsm_trace_enable,
+    nsm_trace_read,
 )
 
 

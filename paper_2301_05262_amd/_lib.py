@@ -20,7 +20,7 @@ FEATURE_SETS = {"hard6": 0, "soft8": 1}
 EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
     "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
-    "nsm_forward", "nsm_backward",
+    "nsm_forward", "nsm_backward", "nsm_trace_enable", "nsm_trace_read",
 ]
 
 
@@ -73,6 +73,9 @@ def load():
         "nsm_workspace_bytes": ([vp, i32, i32, i32, i32, psz], i32),
         "nsm_forward": ([vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "nsm_backward": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+        "nsm_trace_enable": ([i32], i32),
+        "nsm_trace_read": ([i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float),
+                            ctypes.POINTER(ctypes.c_int)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -194,3 +197,20 @@ def nsm_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, worksp
     _check(load().nsm_backward(ctx, _ptr(feat), _ptr(dvis), n, h, w, _ptr(dw_out), int(accumulate),
                                _ptr(dfeat_out), _ptr(workspace), ws_bytes, _stream(stream)),
            "nsm_backward")
+
+
+def nsm_trace_enable(on=True):
+    _check(load().nsm_trace_enable(int(bool(on))), "nsm_trace_enable")
+
+
+def nsm_trace_read(max_records=4096):
+    """[(kernel name, milliseconds)] recorded since the last read."""
+    names = ctypes.create_string_buffer(64 * max_records)
+    ms = (ctypes.c_float * max_records)()
+    n = ctypes.c_int()
+    _check(load().nsm_trace_read(max_records, names, ms, ctypes.byref(n)), "nsm_trace_read")
+    out = []
+    raw = names.raw
+    for i in range(min(n.value, max_records)):
+        out.append((raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode(), float(ms[i])))
+    return out

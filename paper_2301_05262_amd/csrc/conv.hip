@@ -374,6 +374,10 @@ constexpr size_t packed_bytes() {
     X(8, 0, 16, Store, false, 8)                \
     X(8, 16, 8, Head, false, 8)
 
+template <Dt D> constexpr const char* dt_suffix() {
+    return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : " f16");
+}
+
 template <Dt D>
 hipError_t launch(const ConvStage& st, OutMode mode, const ConvArgs& a, hipStream_t s, bool* found) {
 #define NSM_CASE(CS_, CU_, CO_, MODE_, F32_, TH_)                                              \
@@ -381,6 +385,7 @@ hipError_t launch(const ConvStage& st, OutMode mode, const ConvArgs& a, hipStrea
         a.in_f32 == F32_) {                                                                    \
         *found = true;                                                                         \
         dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH_ - 1) / TH_, a.n);                          \
+        TraceScope ts("conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_, dt_suffix<D>(), s);      \
         k_conv3x3<D, F32_, CS_, CU_, CO_, OutMode::MODE_, TH_><<<grid, kThreads, 0, s>>>(a);   \
         return hipGetLastError();                                                              \
     }

@@ -9,6 +9,23 @@
 
 namespace nsm {
 
+// ------------------------------------------------------------- tracing
+// Per-kernel timing hooks (no-ops unless nsm_trace_enable(1) was called).
+bool trace_on();
+void trace_begin(const char* name, const char* suffix, hipStream_t s);
+void trace_end(hipStream_t s);
+
+struct TraceScope {
+    hipStream_t s;
+    bool on;
+    TraceScope(const char* name, const char* suffix, hipStream_t st) : s(st), on(trace_on()) {
+        if (on) trace_begin(name, suffix, s);
+    }
+    ~TraceScope() {
+        if (on) trace_end(s);
+    }
+};
+
 // ------------------------------------------------------------ rasteriser
 // 64-byte per-triangle record written by the setup kernel.
 struct alignas(16) TriSetup {

@@ -351,22 +351,35 @@ hipError_t raster(const float* tris, int n_tris, const Mat4& m, int w, int h, bo
                   void* out, void* ws, hipStream_t s) {
     const size_t npix = (size_t)w * (size_t)h;
     const int fill_blocks = (int)min((size_t)4096, (npix + 255) / 256);
-    if (key64)
-        k_fill_u64<<<fill_blocks, 256, 0, s>>>(reinterpret_cast<unsigned long long*>(out), npix, kEmptyKey);
-    else
-        k_fill_u32<<<fill_blocks, 256, 0, s>>>(reinterpret_cast<uint32_t*>(out), npix, kEmptyDepth);
+    const char* sfx = key64 ? " camera" : " light";
+    {
+        TraceScope ts("clear", sfx, s);
+        if (key64)
+            k_fill_u64<<<fill_blocks, 256, 0, s>>>(reinterpret_cast<unsigned long long*>(out), npix, kEmptyKey);
+        else
+            k_fill_u32<<<fill_blocks, 256, 0, s>>>(reinterpret_cast<uint32_t*>(out), npix, kEmptyDepth);
+    }
     if (n_tris == 0) return hipGetLastError();
     char* base = reinterpret_cast<char*>(ws);
     TriSetup* setup = reinterpret_cast<TriSetup*>(base);
     int* counts = reinterpret_cast<int*>(base + align256((size_t)n_tris * sizeof(TriSetup)));
     long long* offsets =
         reinterpret_cast<long long*>(reinterpret_cast<char*>(counts) + align256((size_t)n_tris * 4));
-    k_tri_setup<<<(n_tris + 255) / 256, 256, 0, s>>>(tris, n_tris, m, w, h, setup, counts);
-    k_scan<<<1, kScanThreads, 0, s>>>(counts, n_tris, offsets);
-    if (key64)
-        k_raster<true><<<kRasterBlocks, 256, 0, s>>>(setup, offsets, n_tris, w, h, out);
-    else
-        k_raster<false><<<kRasterBlocks, 256, 0, s>>>(setup, offsets, n_tris, w, h, out);
+    {
+        TraceScope ts("tri_setup", sfx, s);
+        k_tri_setup<<<(n_tris + 255) / 256, 256, 0, s>>>(tris, n_tris, m, w, h, setup, counts);
+    }
+    {
+        TraceScope ts("tile_scan", sfx, s);
+        k_scan<<<1, kScanThreads, 0, s>>>(counts, n_tris, offsets);
+    }
+    {
+        TraceScope ts("raster", sfx, s);
+        if (key64)
+            k_raster<true><<<kRasterBlocks, 256, 0, s>>>(setup, offsets, n_tris, w, h, out);
+        else
+            k_raster<false><<<kRasterBlocks, 256, 0, s>>>(setup, offsets, n_tris, w, h, out);
+    }
     return hipGetLastError();
 }
 
@@ -375,6 +388,7 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
                   uint8_t* mask, hipStream_t s) {
     dim3 grid((w + 255) / 256, h);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
+    TraceScope ts("gather", soft ? " soft8" : " hard6", s);
     if (soft)
         k_gather<true><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
     else
