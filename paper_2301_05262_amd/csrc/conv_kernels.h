@@ -1,0 +1,394 @@
+// Fused 3x3 convolution stages of the shadow U-Net as MFMA implicit GEMM.
+//
+// The network (paper Sec. 4.5) is a U-Net trimmed to one 3x3 convolution per
+// level with bilinear upsampling; the paper's measurements (supplemental
+// Sec. 3, layer-wise table) show its runtime follows the size of the
+// temporary buffers rather than the flop count, so every stage here is one
+// kernel that reads its inputs once and writes its outputs once:
+//
+//   prologue   halo tile (TH+2) x (TW+2) pixels -> LDS, in the storage
+//              dtype: zero padding outside the image, float32 features
+//              converted on load, and for decoder stages the concat
+//              [skip, bilinear-x2(lower level)] formed on the fly;
+//   main loop  D[co][px] += W[co][k] * X[k][px] with k = (tap, channel),
+//              weights from a pre-packed global layout (one coalesced
+//              16-byte load per lane per k-group), im2col operand from LDS
+//              (one ds_read_b128 per lane per k-group);
+//   epilogue   bias + ReLU, then one of: store; store + 2x2 max-pool; or the
+//              1x1 head + sigmoid (visibility in [0, 1]).
+//
+// MFMA shapes: float32 uses v_mfma_f32_16x16x4_f32 (4 per k-group of 16),
+// bf16 / fp16 use v_mfma_f32_16x16x32_{bf16,f16} (1 per k-group of 32); all
+// accumulate in float32.  Rows of the MFMA are output channels, columns are
+// 16 consecutive pixels of one image row, so each lane ends up holding four
+// consecutive channels of one pixel: stores are contiguous NHWC segments.
+//
+// A "block" is 16 bytes of one pixel's channels (4 floats or 8 halves).  The
+// K dimension is the sequence of blocks over (tap, channel block); lane group
+// g = lane / 16 of k-group q reads block 4q + g.  Any assignment of k to
+// (lane group, element) works as long as weights and pixels agree, and this
+// one makes every operand fetch a single 16-byte access.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace nsm {
+namespace ck {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <Dt D> struct DT;
+template <> struct DT<Dt::F32> { using T = float; static constexpr int EPB = 4; };
+template <> struct DT<Dt::BF16> { using T = __bf16; static constexpr int EPB = 8; };
+template <> struct DT<Dt::F16> { using T = _Float16; static constexpr int EPB = 8; };
+
+constexpr int kThreads = 256;
+constexpr int kTW = 32;   // tile width: two 16-pixel MFMA column fragments
+
+__host__ __device__ constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Channel stride (elements) of one LDS pixel: padded so that the byte
+// stride is an odd multiple of 16 (conflict-free 16-byte reads across the
+// 16 pixels of a fragment).
+template <Dt D>
+__host__ __device__ constexpr int lds_stride(int cip) {
+    constexpr int sz = sizeof(typename DT<D>::T);
+    int units = cip * sz / 16;
+    if ((units & 1) == 0) units += 1;
+    return units * 16 / sz;
+}
+
+template <Dt D, int CS, int CU, int CO>
+struct Geo {
+    static constexpr int EPB = DT<D>::EPB;
+    static constexpr int CSP = round_up(CS, EPB);
+    static constexpr int CIP = CSP + CU;
+    static constexpr int BPT = CIP / EPB;        // 16-byte blocks per tap
+    static constexpr int NB = 9 * BPT;           // blocks along K
+    static constexpr int NKG = (NB + 3) / 4;     // k-groups
+    static constexpr int NF = (CO + 15) / 16;    // 16-channel output fragments
+    static constexpr int CST = lds_stride<D>(CIP);
+    static_assert(CU % EPB == 0, "upsampled channels must fill whole blocks");
+};
+
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(_Float16 v) { return (float)v; }
+
+template <typename T> __device__ __forceinline__ T from_f(float v);
+template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float v) { return (__bf16)v; }
+template <> __device__ __forceinline__ _Float16 from_f<_Float16>(float v) { return (_Float16)v; }
+
+template <Dt D>
+__device__ __forceinline__ f32x4 mfma_kgroup(const u32x4& wa, const u32x4& xb, f32x4 acc) {
+    if constexpr (D == Dt::F32) {
+        const f32x4 a = __builtin_bit_cast(f32x4, wa);
+        const f32x4 b = __builtin_bit_cast(f32x4, xb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
+    } else if constexpr (D == Dt::BF16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, wa),
+                                                      __builtin_bit_cast(bf16x8, xb), acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, wa),
+                                                     __builtin_bit_cast(f16x8, xb), acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Pack EPB floats into one 16-byte block of the storage type.
+template <Dt D>
+__device__ __forceinline__ u32x4 pack_block(const float* v) {
+    using T = typename DT<D>::T;
+    constexpr int EPB = DT<D>::EPB;
+    T t[EPB];
+#pragma unroll
+    for (int e = 0; e < EPB; ++e) t[e] = from_f<T>(v[e]);
+    u32x4 r;
+    __builtin_memcpy(&r, t, 16);
+    return r;
+}
+
+template <Dt D>
+__device__ __forceinline__ void unpack_block(const u32x4& r, float* v) {
+    using T = typename DT<D>::T;
+    constexpr int EPB = DT<D>::EPB;
+    T t[EPB];
+    __builtin_memcpy(t, &r, 16);
+#pragma unroll
+    for (int e = 0; e < EPB; ++e) v[e] = to_f(t[e]);
+}
+
+// Halo tile (TH+2) x (kTW+2) pixels of the stage input -> LDS, in the storage
+// dtype, CST elements per pixel: channels [0, CS) from `in` ([n][h][w][CS],
+// float32 when IN_F32, zero-padded up to a whole block), channels
+// [CSP, CSP+CU) from the bilinear x2 upsampling of `low` ([n][h/2][w/2][CU]):
+// source row s = (y + 0.5)/2 - 0.5, taps floor(s) (weight 0.25 for even y,
+// 0.75 for odd y) and floor(s) + 1, both clamped to the low-res image; the
+// same along x.  Pixels outside the image are zero (the conv's padding).
+template <Dt D, bool IN_F32, int CS, int CU, int CST, int TH>
+__device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, const void* in, const void* low,
+                                               int n, int h, int w, int x0, int y0) {
+    using T = typename DT<D>::T;
+    constexpr int EPB = DT<D>::EPB;
+    constexpr int CSP = round_up(CS, EPB);
+    constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
+    constexpr int NCH_S = CSP / EPB, NCH_U = CU / EPB, NCH = NCH_S + NCH_U;
+    for (int idx = threadIdx.x; idx < NPIX * NCH; idx += kThreads) {
+        const int pix = idx / NCH, ch = idx - pix * NCH;
+        const int ty = pix / WP, tx = pix - ty * WP;
+        const int y = y0 + ty - 1, x = x0 + tx - 1;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (y >= 0 && y < h && x >= 0 && x < w) {
+            if (ch < NCH_S) {
+                const size_t p = ((size_t)n * h + y) * w + x;
+                if constexpr (IN_F32) {
+                    const float* src = reinterpret_cast<const float*>(in) + p * CS;
+                    float f[EPB];
+#pragma unroll
+                    for (int e = 0; e < EPB; ++e) {
+                        const int c = ch * EPB + e;
+                        f[e] = (c < CS) ? src[c] : 0.0f;
+                    }
+                    v = pack_block<D>(f);
+                } else {
+                    v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(in) + p * CS + ch * EPB);
+                }
+            } else if constexpr (CU > 0) {
+                const int hl = h >> 1, wl = w >> 1;
+                const int ya = (y - 1) >> 1, xa = (x - 1) >> 1;
+                const float wy0 = (y & 1) ? 0.75f : 0.25f, wx0 = (x & 1) ? 0.75f : 0.25f;
+                const float wy1 = 1.0f - wy0, wx1 = 1.0f - wx0;
+                const int yA = max(ya, 0), yB = min(ya + 1, hl - 1);
+                const int xA = max(xa, 0), xB = min(xa + 1, wl - 1);
+                const T* lo = reinterpret_cast<const T*>(low) + (size_t)n * hl * wl * CU + (ch - NCH_S) * EPB;
+                float f00[EPB], f01[EPB], f10[EPB], f11[EPB], f[EPB];
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yA * wl + xA) * CU), f00);
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yA * wl + xB) * CU), f01);
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yB * wl + xA) * CU), f10);
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yB * wl + xB) * CU), f11);
+#pragma unroll
+                for (int e = 0; e < EPB; ++e)
+                    f[e] = wy0 * (wx0 * f00[e] + wx1 * f01[e]) + wy1 * (wx0 * f10[e] + wx1 * f11[e]);
+                v = pack_block<D>(f);
+            }
+        }
+        *reinterpret_cast<u32x4*>(&tile[pix * CST + ch * EPB]) = v;
+    }
+}
+
+// Store four consecutive channels co..co+3 (fewer at the end of an odd-sized
+// channel vector) of one pixel.
+template <typename T, int CO>
+__device__ __forceinline__ void store4(T* dst, int co, const float* v) {
+    T t4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t4[e] = from_f<T>(v[e]);
+    if constexpr (CO % 4 != 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (co + e < CO) dst[e] = t4[e];
+    } else if constexpr (sizeof(T) == 4) {
+        f32x4 q;
+        __builtin_memcpy(&q, t4, 16);
+        *reinterpret_cast<f32x4*>(dst) = q;
+    } else {
+        uint2 q;
+        __builtin_memcpy(&q, t4, 8);
+        *reinterpret_cast<uint2*>(dst) = q;
+    }
+}
+
+template <Dt D, bool IN_F32, int CS, int CU, int CO, OutMode MODE, int TH>
+__global__ void __launch_bounds__(kThreads) k_conv3x3(ConvArgs a) {
+    using T = typename DT<D>::T;
+    using G = Geo<D, CS, CU, CO>;
+    constexpr int EPB = G::EPB, CST = G::CST, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
+    constexpr int HP = TH + 2, WP = kTW + 2, NPIX = HP * WP;
+    constexpr int RPW = TH / 4;                 // rows per wave
+    constexpr int MF = RPW * 2;                 // M-fragments per wave
+    static_assert(MODE != OutMode::Pool || RPW == 2, "pooling needs row pairs per wave");
+
+    __shared__ __attribute__((aligned(16))) T tile[NPIX * CST];
+
+    const int h = a.h, w = a.w;
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * TH, n = blockIdx.z;
+
+    // ---------------- prologue: halo tile to LDS
+    load_halo_tile<D, IN_F32, CS, CU, CST, TH>(tile, a.in, a.low, n, h, w, x0, y0);
+    __syncthreads();
+
+    // ---------------- main loop
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = lane & 15, g = lane >> 4;
+    const u32x4* wpk = reinterpret_cast<const u32x4*>(a.wpk);
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int q = 0; q < NKG; ++q) {
+        u32x4 wf[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) wf[f] = wpk[(f * NKG + q) * 64 + lane];
+        int b = 4 * q + g;
+        if (b >= NB) b = NB - 1;               // padding k: weights are zero there
+        const int tap = b / BPT, cb = b - tap * BPT;
+        const int ky = tap / 3, kx = tap - ky * 3;
+        const int base = (ky * WP + kx + px) * CST + cb * EPB;
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const int r = wave * RPW + (m >> 1), cf = m & 1;
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + (r * WP + cf * 16) * CST]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[m][f] = mfma_kgroup<D>(wf[f], xb, acc[m][f]);
+        }
+    }
+
+    // ---------------- epilogue
+    if constexpr (MODE != OutMode::Linear) {
+        float bias[NF][4];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = f * 16 + 4 * g + e;
+                bias[f][e] = (co < CO) ? a.bias[co] : 0.0f;
+            }
+#pragma unroll
+        for (int m = 0; m < MF; ++m)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[m][f][e] = fmaxf(acc[m][f][e] + bias[f][e], 0.0f);
+    }
+
+    if constexpr (MODE == OutMode::Head) {
+        float hw[NF][4];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = f * 16 + 4 * g + e;
+                hw[f][e] = (co < CO) ? a.head_w[co] : 0.0f;
+            }
+        const float hb = a.head_w[CO];
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
+            const bool ok = y < h && x < w;
+            const size_t p = ((size_t)n * h + y) * w + x;
+            float s = 0.0f;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s += hw[f][e] * acc[m][f][e];
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (ok && g == 0) {
+                const float logit = s + hb;
+                a.vis[p] = 1.0f / (1.0f + __expf(-logit));
+                if (a.logits) a.logits[p] = logit;
+            }
+            if (ok && a.act_out) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int co = f * 16 + 4 * g;
+                    if (co < CO) *reinterpret_cast<f32x4*>(a.act_out + p * CO + co) = acc[m][f];
+                }
+            }
+        }
+    } else {
+        T* out = reinterpret_cast<T*>(a.out);
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
+            if (y < h && x < w) {
+                const size_t p = ((size_t)n * h + y) * w + x;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int co = f * 16 + 4 * g;
+                    if (co < CO) {
+                        float v4[4] = {acc[m][f][0], acc[m][f][1], acc[m][f][2], acc[m][f][3]};
+                        store4<T, CO>(out + p * CO + co, co, v4);
+                    }
+                }
+            }
+        }
+        if constexpr (MODE == OutMode::Pool) {
+            T* pooled = reinterpret_cast<T*>(a.pooled);
+            const int hp = h >> 1, wp = w >> 1;
+#pragma unroll
+            for (int cf = 0; cf < 2; ++cf) {
+                const int yp = (y0 >> 1) + wave, xp = ((x0 + cf * 16 + px) >> 1);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    float mx[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float v = fmaxf(acc[cf][f][e], acc[2 + cf][f][e]);
+                        mx[e] = fmaxf(v, __shfl_xor(v, 1));
+                    }
+                    const int co = f * 16 + 4 * g;
+                    if ((px & 1) == 0 && yp < hp && xp < wp && co < CO) {
+                        const size_t p = ((size_t)n * hp + yp) * wp + xp;
+                        store4<T, CO>(pooled + p * CO + co, co, mx);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Weight repack: OHWI float32 [CO][3][3][CS+CU] -> [NF][NKG][64 lanes][EPB]
+// storage type.  With FLIP the source is the forward weight W[CI'][3][3][CO']
+// of a stage whose input gradient this conv computes: the packed kernel is
+// W'[co][ky][kx][ci] = W[ci][2-ky][2-kx][co] (CS = CO', CO = CI', CU = 0).
+template <Dt D, int CS, int CU, int CO, bool FLIP = false>
+__global__ void k_pack(const float* __restrict__ w, void* __restrict__ out) {
+    using T = typename DT<D>::T;
+    using G = Geo<D, CS, CU, CO>;
+    constexpr int EPB = G::EPB;
+    constexpr int total = G::NF * G::NKG * 64 * EPB;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int e = idx % EPB;
+    const int lane = (idx / EPB) % 64;
+    const int q = (idx / (EPB * 64)) % G::NKG;
+    const int f = idx / (EPB * 64 * G::NKG);
+    const int co = f * 16 + (lane & 15);
+    const int b = 4 * q + (lane >> 4);
+    float v = 0.0f;
+    if (b < G::NB && co < CO) {
+        const int tap = b / G::BPT, cb = b % G::BPT;
+        const int c = cb * EPB + e;
+        int ci = -1;
+        if (c < G::CSP) ci = (c < CS) ? c : -1;
+        else ci = CS + (c - G::CSP);
+        if (ci >= 0) {
+            if constexpr (FLIP)
+                v = w[((size_t)ci * 9 + (8 - tap)) * CO + co];
+            else
+                v = w[((size_t)co * 9 + tap) * (CS + CU) + ci];
+        }
+    }
+    reinterpret_cast<T*>(out)[idx] = from_f<T>(v);
+}
+
+template <Dt D, int CS, int CU, int CO>
+constexpr size_t packed_bytes() {
+    using G = Geo<D, CS, CU, CO>;
+    return (size_t)G::NF * G::NKG * 64 * 16;
+}
+
+}  // namespace ck
+}  // namespace nsm

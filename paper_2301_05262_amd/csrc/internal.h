@@ -74,7 +74,7 @@ size_t packed_weight_bytes(const ConvStage& st, Dt dt);
 hipError_t pack_weights(const ConvStage& st, Dt dt, const float* w_ohwi, void* packed,
                         hipStream_t s);
 
-enum class OutMode { Store = 0, Pool = 1, Head = 2 };
+enum class OutMode { Store = 0, Pool = 1, Head = 2, Linear = 3 };  // Linear: no bias, no ReLU
 
 struct ConvArgs {
     const void* in;      // plain input [n][h][w][cs] (float32 when in_f32, else the stage dtype)
@@ -92,5 +92,26 @@ struct ConvArgs {
 };
 hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs& a, hipStream_t s);
 bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32);
+
+// ------------------------------------------------------ backward (float32)
+bool backward_supported(const ConvStage& st);
+size_t head_partial_floats(int c0, size_t npix);
+hipError_t head_backward(int c0, const float* vis, const float* dvis, const float* act,
+                         const float* head_w, size_t npix, float* dz, float* partial, hipStream_t s);
+hipError_t head_reduce(int c0, const float* partial, size_t npix, float* dw, bool accumulate,
+                       hipStream_t s);
+// dz_low = upsample^T(dup[..., c_off : c_off + c]) * (act_low > 0)
+hipError_t up_transpose_mask(int c, int ci_total, int c_off, const float* dup, const float* act_low,
+                             int n, int hl, int wl, float* dz_low, hipStream_t s);
+// dz = (dskip[..., :c] + maxpool^T(dpool)) * (act > 0)
+hipError_t pool_transpose_mask(int c, int ci_total, const float* dskip, const float* dpool,
+                               const float* act, int n, int h, int w, float* dz, hipStream_t s);
+size_t wgrad_partial_floats(const ConvStage& st, int n, int h, int w);
+hipError_t conv_wgrad(const ConvStage& st, const float* in, const float* low, const float* dz, int n,
+                      int h, int w, float* partial, float* dw, float* db, bool accumulate, hipStream_t s);
+size_t dgrad_packed_bytes(const ConvStage& st);
+hipError_t pack_dgrad_weights(const ConvStage& st, const float* w_ohwi, void* packed, hipStream_t s);
+hipError_t conv_dgrad(const ConvStage& st, const void* wpk, const float* dz, int n, int h, int w,
+                      float* dx, hipStream_t s);
 
 }  // namespace nsm

@@ -4,6 +4,7 @@
 // stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -29,6 +30,7 @@ struct StagePlan {
     size_t w_off;       // offset (floats) of the OHWI weights in the flat vector
     size_t b_off;       // offset (floats) of the biases
     size_t pk_off;      // byte offset of packed weights in the device buffer
+    size_t pk_bwd_off;  // byte offset of the input-gradient (flipped) pack, FP32 only
 };
 
 bool device_ok() {
@@ -49,6 +51,7 @@ struct nsm_ctx {
     size_t dbuf_bytes = 0;
     size_t flat_off = 0;             // byte offset of the float32 flat copy
     bool has_weights = false;
+    bool trainable = false;          // FP32 context with backward kernels for every stage
 };
 
 extern "C" {
@@ -178,6 +181,15 @@ nsm_status nsm_create(const nsm_net_desc* desc, nsm_dtype dtype, nsm_ctx** out) 
         p.pk_off = pk;
         pk += align256(packed_weight_bytes(p.st, c->dt));
     }
+    // the FP32 context also keeps the flipped/transposed packs its input-gradient convs use
+    c->trainable = c->dt == Dt::F32;
+    for (auto& p : c->stages) c->trainable = c->trainable && backward_supported(p.st);
+    if (c->trainable) {
+        for (auto& p : c->stages) {
+            p.pk_bwd_off = pk;
+            pk += align256(dgrad_packed_bytes(p.st));
+        }
+    }
     c->flat_off = pk;
     c->dbuf_bytes = pk + align256(c->n_params * 4);
     *out = c;
@@ -211,9 +223,13 @@ nsm_status nsm_set_weights(nsm_ctx* ctx, const float* w, size_t n, void* stream)
     char* base = reinterpret_cast<char*>(ctx->dbuf);
     float* flat = reinterpret_cast<float*>(base + ctx->flat_off);
     if (hipMemcpyAsync(flat, w, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return NSM_E_DEVICE;
-    for (const auto& p : ctx->stages)
+    for (const auto& p : ctx->stages) {
         if (pack_weights(p.st, ctx->dt, flat + p.w_off, base + p.pk_off, s) != hipSuccess)
             return NSM_E_LAUNCH;
+        if (ctx->trainable &&
+            pack_dgrad_weights(p.st, flat + p.w_off, base + p.pk_bwd_off, s) != hipSuccess)
+            return NSM_E_LAUNCH;
+    }
     ctx->has_weights = true;
     return NSM_OK;
 }
@@ -302,6 +318,103 @@ hipError_t run_forward(const nsm_ctx* c, const float* feat, int n, int h, int w,
     return hipSuccess;
 }
 
+// Training workspace: the float32 forward activations (including the last
+// decoder activation and the visibility) plus every gradient buffer.
+struct TrainLayout {
+    FwdLayout f;
+    size_t vis, dzD[4], dxD[4], dzB, dp[4], head_part, wg_part, total;
+};
+
+TrainLayout plan_training(const nsm_ctx* c, int n, int h, int w) {
+    TrainLayout T{};
+    T.f = plan_forward(c, n, h, w, true);
+    const int lv = c->desc.levels;
+    const int* wd = c->desc.widths;
+    size_t off = T.f.total;
+    auto take = [&](size_t floats) {
+        size_t o = off;
+        off += align256(floats * 4);
+        return o;
+    };
+    auto px = [&](int l) { return (size_t)n * (size_t)(h >> l) * (size_t)(w >> l); };
+    T.vis = take(px(0));
+    for (int l = 0; l < lv - 1; ++l) {
+        T.dzD[l] = take(px(l) * wd[l]);
+        T.dxD[l] = take(px(l) * (wd[l] + wd[l + 1]));
+        T.dp[l] = take(px(l + 1) * wd[l]);
+    }
+    T.dzB = take(px(lv - 1) * wd[lv - 1]);
+    T.head_part = take(head_partial_floats(wd[0], px(0)));
+    size_t wg = 0;
+    for (const auto& p : c->stages)
+        wg = std::max(wg, wgrad_partial_floats(p.st, n, h >> p.level, w >> p.level));
+    T.wg_part = take(wg);
+    T.total = off;
+    return T;
+}
+
+hipError_t run_backward(const nsm_ctx* c, const float* feat, const float* dvis, int n, int h, int w,
+                        float* dw, bool acc, float* dfeat, char* ws, const TrainLayout& T,
+                        hipStream_t s) {
+    const char* base = reinterpret_cast<const char*>(c->dbuf);
+    const float* flat = reinterpret_cast<const float*>(base + c->flat_off);
+    const int lv = c->desc.levels;
+    const int* wd = c->desc.widths;
+    const FwdLayout& L = T.f;
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+    const auto& st = c->stages;
+    auto enc = [&](int l) -> const StagePlan& { return st[l]; };
+    const StagePlan& bott = st[lv - 1];
+    auto dec = [&](int l) -> const StagePlan& { return st[2 * lv - 2 - l]; };
+    float* part = F(T.wg_part);
+    hipError_t e;
+#define NSM_TRY(x) \
+    if ((e = (x)) != hipSuccess) return e
+    // recompute the forward, keeping every activation (float32)
+    NSM_TRY(run_forward(c, feat, n, h, w, F(T.vis), nullptr, ws, L, F(L.d0act), s));
+    // sigmoid + 1x1 head
+    const size_t npix = (size_t)n * h * w;
+    NSM_TRY(head_backward(wd[0], F(T.vis), dvis, F(L.d0act), flat + c->head_w_off, npix, F(T.dzD[0]),
+                          F(T.head_part), s));
+    NSM_TRY(head_reduce(wd[0], F(T.head_part), npix, dw + c->head_w_off, acc, s));
+    // decoder stages, top level first
+    for (int l = 0; l < lv - 1; ++l) {
+        const StagePlan& p = dec(l);
+        const int hl = h >> l, wl = w >> l;
+        const float* lower = (l == lv - 2) ? F(L.bott) : F(L.dec[l + 1]);
+        NSM_TRY(conv_dgrad(p.st, base + p.pk_bwd_off, F(T.dzD[l]), n, hl, wl, F(T.dxD[l]), s));
+        NSM_TRY(conv_wgrad(p.st, F(L.skip[l]), lower, F(T.dzD[l]), n, hl, wl, part, dw + p.w_off,
+                           dw + p.b_off, acc, s));
+        float* target = (l == lv - 2) ? F(T.dzB) : F(T.dzD[l + 1]);
+        NSM_TRY(up_transpose_mask(wd[l + 1], wd[l] + wd[l + 1], wd[l], F(T.dxD[l]), lower, n, hl >> 1,
+                                  wl >> 1, target, s));
+    }
+    // bottleneck
+    {
+        const int hb = h >> (lv - 1), wb = w >> (lv - 1);
+        NSM_TRY(conv_dgrad(bott.st, base + bott.pk_bwd_off, F(T.dzB), n, hb, wb, F(T.dp[lv - 2]), s));
+        NSM_TRY(conv_wgrad(bott.st, F(L.pool[lv - 2]), nullptr, F(T.dzB), n, hb, wb, part,
+                           dw + bott.w_off, dw + bott.b_off, acc, s));
+    }
+    // encoder stages, bottom level first
+    for (int l = lv - 2; l >= 0; --l) {
+        const StagePlan& p = enc(l);
+        const int hl = h >> l, wl = w >> l;
+        float* dz = F(T.dzD[l]);     // the decoder gradient at this level is no longer needed
+        NSM_TRY(pool_transpose_mask(wd[l], wd[l] + wd[l + 1], F(T.dxD[l]), F(T.dp[l]), F(L.skip[l]), n,
+                                    hl, wl, dz, s));
+        const float* in = (l == 0) ? feat : F(L.pool[l - 1]);
+        NSM_TRY(conv_wgrad(p.st, in, nullptr, dz, n, hl, wl, part, dw + p.w_off, dw + p.b_off, acc, s));
+        if (l > 0) {
+            NSM_TRY(conv_dgrad(p.st, base + p.pk_bwd_off, dz, n, hl, wl, F(T.dp[l - 1]), s));
+        } else if (dfeat) {
+            NSM_TRY(conv_dgrad(p.st, base + p.pk_bwd_off, dz, n, hl, wl, dfeat, s));
+        }
+    }
+#undef NSM_TRY
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -310,7 +423,11 @@ nsm_status nsm_workspace_bytes(const nsm_ctx* ctx, int n, int h, int w, int trai
     if (!ctx || !bytes) return NSM_E_INVALID_ARG;
     nsm_status st = check_net_shape(ctx, n, h, w);
     if (st != NSM_OK) return st;
-    if (training) return NSM_E_UNSUPPORTED;
+    if (training) {
+        if (!ctx->trainable) return NSM_E_UNSUPPORTED;
+        *bytes = plan_training(ctx, n, h, w).total;
+        return NSM_OK;
+    }
     *bytes = plan_forward(ctx, n, h, w, false).total;
     return NSM_OK;
 }
@@ -334,10 +451,19 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
 nsm_status nsm_backward(nsm_ctx* ctx, const float* feat, const float* dvis, int n, int h, int w,
                         float* dw_out, int accumulate, float* dfeat_out, void* workspace,
                         size_t ws_bytes, void* stream) {
-    (void)feat; (void)dvis; (void)n; (void)h; (void)w; (void)dw_out; (void)accumulate;
-    (void)dfeat_out; (void)workspace; (void)ws_bytes; (void)stream;
-    if (!ctx) return NSM_E_INVALID_ARG;
-    return NSM_E_UNSUPPORTED;
+    if (!ctx || !feat || !dvis || !dw_out) return NSM_E_INVALID_ARG;
+    nsm_status st = check_net_shape(ctx, n, h, w);
+    if (st != NSM_OK) return st;
+    if (!ctx->trainable) return NSM_E_UNSUPPORTED;
+    if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
+    TrainLayout T = plan_training(ctx, n, h, w);
+    if (!workspace || ws_bytes < T.total) return NSM_E_WORKSPACE;
+    if (!device_ok()) return NSM_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (run_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate != 0, dfeat_out,
+                     reinterpret_cast<char*>(workspace), T, s) != hipSuccess)
+        return NSM_E_LAUNCH;
+    return NSM_OK;
 }
 
 }  // extern "C"

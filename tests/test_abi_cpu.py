@@ -70,8 +70,20 @@ def test_create_validation_and_param_counts():
         assert e.value.status == 1
     finally:
         nsm.nsm_destroy(ctx)
+    ctx = nsm.nsm_create(6, (16, 32, 64), "f32")
+    assert nsm.nsm_workspace_bytes(ctx, 2, 64, 64, training=1) > nsm.nsm_workspace_bytes(ctx, 2, 64, 64)
+    with pytest.raises(nsm.NsmError) as e:        # backward before set_weights
+        nsm.nsm_backward(ctx, 1024, 2048, 1, 64, 64, 4096, 0, None, 8192, 1 << 30, 0)
+    assert e.value.status == 5
+    nsm.nsm_destroy(ctx)
     ctx = nsm.nsm_create(6, (8, 16), "bf16")
     assert nsm.nsm_param_count(ctx) == 3353
+    with pytest.raises(nsm.NsmError) as e:        # the differentiation form is float32 only
+        nsm.nsm_workspace_bytes(ctx, 1, 64, 64, training=1)
+    assert e.value.status == 3
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_backward(ctx, 1024, 2048, 1, 64, 64, 4096, 0, None, 8192, 1 << 30, 0)
+    assert e.value.status == 3
     nsm.nsm_destroy(ctx)
     with pytest.raises(nsm.NsmError) as e:
         nsm.nsm_create(6, (16, 32, 48), "f32")                  # no kernels for this width set
