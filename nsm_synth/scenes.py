@@ -107,27 +107,36 @@ def box_tris(centre, half):
     return _orient_outward(np.array(tris), centre)
 
 
-def uv_sphere_tris(centre, radius, slices=20, stacks=17):
-    """UV sphere: two pole fans plus (stacks - 2) quad bands."""
-    centre = np.asarray(centre, np.float64)
+_SPHERE_TEMPLATES = {}
 
-    def vert(i, j):
-        th = math.pi * i / stacks
-        ph = 2.0 * math.pi * (j % slices) / slices
-        return centre + radius * np.array(
-            [math.sin(th) * math.cos(ph), math.cos(th), math.sin(th) * math.sin(ph)])
 
-    tris = []
-    for j in range(slices):
-        tris.append([vert(0, 0), vert(1, j), vert(1, j + 1)])
-        tris.append([vert(stacks, 0), vert(stacks - 1, j + 1), vert(stacks - 1, j)])
-    for i in range(1, stacks - 1):
+def _unit_sphere(slices, stacks):
+    """Unit-sphere directions per triangle vertex, outward-oriented (cached)."""
+    key = (slices, stacks)
+    if key not in _SPHERE_TEMPLATES:
+        def vert(i, j):
+            th = math.pi * i / stacks
+            ph = 2.0 * math.pi * (j % slices) / slices
+            return np.array([math.sin(th) * math.cos(ph), math.cos(th), math.sin(th) * math.sin(ph)])
+
+        tris = []
         for j in range(slices):
-            a, b = vert(i, j), vert(i, j + 1)
-            c, d = vert(i + 1, j), vert(i + 1, j + 1)
-            tris.append([a, c, d])
-            tris.append([a, d, b])
-    return _orient_outward(np.array(tris), centre)
+            tris.append([vert(0, 0), vert(1, j), vert(1, j + 1)])
+            tris.append([vert(stacks, 0), vert(stacks - 1, j + 1), vert(stacks - 1, j)])
+        for i in range(1, stacks - 1):
+            for j in range(slices):
+                a, b = vert(i, j), vert(i, j + 1)
+                c, d = vert(i + 1, j), vert(i + 1, j + 1)
+                tris.append([a, c, d])
+                tris.append([a, d, b])
+        _SPHERE_TEMPLATES[key] = _orient_outward(np.array(tris), np.zeros(3))
+    return _SPHERE_TEMPLATES[key]
+
+
+def uv_sphere_tris(centre, radius, slices=20, stacks=17):
+    """UV sphere: two pole fans plus (stacks - 2) quad bands, outward winding."""
+    centre = np.asarray(centre, np.float64)
+    return centre + radius * _unit_sphere(slices, stacks)
 
 
 def ground_quad(y=-1.0, half=1.5, cells=1):
