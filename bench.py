@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", default="frame", choices=["frame", "none"])
     ap.add_argument("--forms", default="bf16,f32,f16")
+    ap.add_argument("--batched", type=int, default=1, help="also time the 16-frame graph batch")
     return ap.parse_args()
 
 
@@ -66,6 +67,60 @@ def stage_costs(widths, c_in, h, w, dtype):
     fl, by = out[k]
     out[k] = (fl + 2.0 * L0 * w0, by)          # the fused 1x1 head
     return out
+
+
+def batched_section(S, torch, seed, reps):
+    """16 mixed-size frames (1280x720 / 1920x1080 / 2560x1440, 20k-100k triangles,
+    hard and soft lights): features + SOFT8 BF16 network per size group, one
+    captured graph per batch, against one-by-one FP32 launches."""
+    from paper_2301_05262_amd.api import ShadowNet
+    from paper_2301_05262_amd.batch import BatchedPipeline
+    frames = S.make_batched_frames(seed, 16)
+    flat = torch.from_numpy(S.he_weights(S.U3_SOFT, seed))
+    pipe = BatchedPipeline(frames, 8, S.U3_SOFT.widths, flat, "bf16")
+    pipe.capture()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        pipe.replay()
+    batch_ms = []
+    for _ in range(reps):
+        a, b = ev(), ev()
+        a.record()
+        pipe.replay()
+        b.record()
+        b.synchronize()
+        batch_ms.append(a.elapsed_time(b))
+    net32 = ShadowNet(8, S.U3_SOFT.widths, "f32")
+    net32.set_weights(flat)
+    slots = []
+    for g in pipe.groups:
+        for k, i in enumerate(g["idx"]):
+            slots.append((i, g["bufs"][k], g["feat"][k].unsqueeze(0), torch.empty_like(g["vis"][k:k + 1])))
+    for i, buf, f, v in slots:                       # warm-up (workspaces)
+        pipe.builders[i](frames[i][1], soft=True, out=buf)
+        net32.forward(f, vis_out=v)
+    torch.cuda.synchronize()
+    frame_ms = []
+    for _ in range(max(1, reps // 4)):
+        for i, buf, f, v in slots:
+            a, b = ev(), ev()
+            a.record()
+            pipe.builders[i](frames[i][1], soft=True, out=buf)
+            net32.forward(f, vis_out=v)
+            b.record()
+            b.synchronize()
+            frame_ms.append(a.elapsed_time(b))
+    mpx = sum(fr.width * fr.height for _, fr in frames) / 1e6
+    bm, fm = np.array(batch_ms), np.array(frame_ms)
+    return {
+        "workload": "batched_mixed", "frames": len(frames), "megapixels": mpx,
+        "tris": [sc.n_tris for sc, _ in frames],
+        "graph_bf16": {"ms_per_batch_p50": float(np.median(bm)), "ms_per_batch_p99": float(np.quantile(bm, 0.99)),
+                       "frames_per_s": len(frames) / (float(bm.mean()) / 1e3),
+                       "note": "all frames of a batch complete together: per-frame latency = batch time"},
+        "one_by_one_f32": {"ms_per_frame_p50": float(np.median(fm)), "ms_per_frame_p99": float(np.quantile(fm, 0.99)),
+                           "frames_per_s": 1e3 / float(fm.mean())},
+    }
 
 
 def main():
@@ -195,6 +250,12 @@ def main():
                     "unit": "GB/s", "frac": (by / t) / HBM_PEAK}
         roof.update({"traffic": None, "avg_us": kern[dom]["avg_us"], "algorithmic_bytes": by,
                      "algorithmic_flops": fl})
+    batched = None
+    if args.batched:
+        batched = batched_section(S, torch, args.seed, reps=20)
+        print(f"[bench] batched: {batched['graph_bf16']['frames_per_s']:.0f} frames/s (graph, bf16) vs "
+              f"{batched['one_by_one_f32']['frames_per_s']:.0f} frames/s (one by one, f32)",
+              file=sys.stderr, flush=True)
     ms = results[head]["ms_per_frame"]
     line = {
         "metric": METRIC, "value": ms, "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
@@ -203,7 +264,7 @@ def main():
         "config": {"workload": WORKLOAD, "width": W, "height": H, "sm_size": fr.sm_size,
                    "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
                    "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
-        "forms": results, "roofline": roof, "cpu_baseline": cpu,
+        "forms": results, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
     }
     print(json.dumps(line))
 

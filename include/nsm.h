@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define NSM_ABI_VERSION 1
+#define NSM_ABI_VERSION 2
 
 typedef enum {
     NSM_OK = 0,
@@ -55,29 +55,46 @@ typedef enum {
 typedef enum { NSM_F32 = 0, NSM_BF16 = 1, NSM_F16 = 2 } nsm_dtype;
 
 /* Feature sets (channel order, NHWC, float32):
- *   HARD6: [d/f_C, n.x, n.y, n.z, (z - z_f)/f_L, z/f_L]
- *   SOFT8: HARD6 + [r_e/0.2, z_blk/f_L]
+ *   HARD6:  [d/f_C, n.x, n.y, n.z, (z - z_f)/f_L, z/f_L]
+ *   SOFT8:  HARD6 + [r_e/0.2, z_blk/f_L]
+ *   PAPER4: [c_e + r_e/0.0625, z/z_f, (z - z_f)/f_L, c_c/d], the set the paper
+ *           selects (Sec. 3.2); c_e = n.l and c_c = n.v are the cosines with
+ *           the emitter and view directions, and the emitter size enters as a
+ *           DC offset on c_e on the paper's 0..4 scale (Sec. 3.1.1; 4 = radius
+ *           0.25 scene units, i.e. a 50 cm diameter with metres as units).
  * d: view depth along the camera axis; n: face normal turned towards the
  * camera; z: light-view linear depth stored in the shadow map at the
  * receiver's texel; z_f: the receiver's own light-view linear depth; r_e:
  * emitter radius; z_blk: mean linear depth of the 7x7 map texels in front
  * of the receiver (z_f when there are none).  Background pixels are 0. */
-typedef enum { NSM_FEAT_HARD6 = 0, NSM_FEAT_SOFT8 = 1 } nsm_feature_set;
+typedef enum { NSM_FEAT_HARD6 = 0, NSM_FEAT_SOFT8 = 1, NSM_FEAT_PAPER4 = 2 } nsm_feature_set;
 
 typedef struct nsm_ctx nsm_ctx;
 
-/* U-Net descriptor: `levels` resolution levels with channel widths
- * widths[0..levels-1].  Stages, in execution order: encoder 3x3 conv + ReLU
- * + 2x2 max-pool for levels 0..L-2, bottleneck 3x3 conv + ReLU at level
- * L-1, decoder bilinear x2 upsample, concat [skip, up], 3x3 conv + ReLU for
- * levels L-2..0, then a 1x1 head to one channel and a sigmoid (one 3x3 conv
- * per level and bilinear upsampling follow Sec. 4.5).
- * Supported: c_in in {6, 8}; widths {8, 16} (levels 2) or {16, 32, 64}
- * (levels 3). */
+/* Network architectures.
+ * NSM_ARCH_UNET: `levels` resolution levels with channel widths
+ *   widths[0..levels-1].  Stages, in execution order: encoder 3x3 conv +
+ *   ReLU + 2x2 max-pool for levels 0..L-2, bottleneck 3x3 conv + ReLU at
+ *   level L-1, decoder bilinear x2 upsample, concat [skip, up], 3x3 conv +
+ *   ReLU for levels L-2..0, then a 1x1 head to one channel and a sigmoid
+ *   (one 3x3 conv per level and bilinear upsampling follow Sec. 4.5).
+ *   Supported: c_in in {6, 8}; widths {8, 16} or {16, 32, 64}.
+ * NSM_ARCH_PAPER: the paper's trimmed network (Sec. 4.5): per level a 3x3
+ *   and a 1x1 conv (each + ReLU); 2x2 average pooling; decoder input
+ *   up(y_{l+1}) + x_l (sum skip) for l >= 1 and up(y_1) alone at level 0;
+ *   encoder level l: 3x3 C_{l-1} -> w_l, 1x1 w_l -> w_l; bottleneck: 3x3
+ *   w_{L-2} -> w_{L-1}, 1x1 w_{L-1} -> w_{L-2}; decoder level l >= 1:
+ *   3x3 w_l -> w_l, 1x1 w_l -> w_{l-1}; level 0: 3x3 and 1x1 w_0 -> w_0,
+ *   then a 1x1 output conv to one channel and a sigmoid.  Flat parameters
+ *   list the convs in that order (each OHWI weights then biases).
+ *   Supported: c_in = 4; widths {16, 32, 64} or {16, 32, 64, 128, 256}. */
+typedef enum { NSM_ARCH_UNET = 0, NSM_ARCH_PAPER = 1 } nsm_arch;
+
 typedef struct nsm_net_desc {
+    int32_t arch;       /* nsm_arch */
     int32_t c_in;
     int32_t levels;
-    int32_t widths[4];
+    int32_t widths[8];
 } nsm_net_desc;
 
 /* Per-frame light and camera (host struct, float32).  Matrices are
@@ -115,7 +132,7 @@ const char *nsm_status_str(int status);
  *   tri_normals [n_tris][3] float32 unit face normals.
  *   fp          host; light and camera for this frame.
  *   h, w        screen size (1..8192 each).
- *   fs          feature set (HARD6 or SOFT8).
+ *   fs          feature set (HARD6, SOFT8 or PAPER4).
  *   gbuf_in     [h][w] uint64 camera key buffer to use as the G-buffer, or
  *               NULL to rasterise it from `tris` with fp->m_cam.
  *   gbuf_out    [h][w] uint64; where the camera raster writes when gbuf_in
@@ -123,7 +140,7 @@ const char *nsm_status_str(int status);
  *               depth_bits << 32 | triangle id, all ones where empty.
  *   sm_out      [S][S] uint32 light-view depth bits (float32 ndc depth in
  *               [0, 1], +inf bits where empty).
- *   feat_out    [h][w][C] float32, C = 6 (HARD6) or 8 (SOFT8).
+ *   feat_out    [h][w][C] float32, C = 6 (HARD6), 8 (SOFT8) or 4 (PAPER4).
  *   mask_out    [h][w] uint8 hard depth-test result (1 = shadowed), or NULL.
  * The rasteriser and the gather are deterministic: repeated calls give
  * identical bits.  Triangles with a vertex at w_clip <= 1e-6 or beyond the
@@ -169,7 +186,7 @@ nsm_status nsm_workspace_bytes(const nsm_ctx *ctx, int n, int h, int w, int trai
 nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
                        float *logits_out, void *workspace, size_t ws_bytes, void *stream);
 
-/* nsm_backward -- gradient of sum(dvis * vis) (FP32 contexts only).
+/* nsm_backward -- gradient of sum(dvis * vis) (FP32 NSM_ARCH_UNET contexts).
  * Recomputes the forward activations into the workspace, then applies the
  * adjoint of every stage.
  *   dvis       [n][h][w] float32 upstream gradient.

@@ -103,11 +103,15 @@ def raster(tris, matrix, width, height, mode="depth"):
     return out, tuple(int(s) for s in stats)
 
 
-def gather(scene, fr, gbuf, sm, soft=False):
+FEATURE_SETS = {"hard6": (0, 6), "soft8": (1, 8), "paper4": (2, 4)}
+
+
+def gather(scene, fr, gbuf, sm, soft=False, fs=None):
     """Feature gather. Returns dict(feat [H,W,C] f32, mask [H,W] u8,
-    pos [H,W,3] f32, aux [H,W,4] f32 = (z, z_f, beta, inside))."""
+    pos [H,W,3] f32, aux [H,W,4] f32 = (z, z_f, beta, inside)).
+    fs: 'hard6', 'soft8' or 'paper4' (default from `soft`)."""
     h, w = fr.height, fr.width
-    C = 8 if soft else 6
+    code, C = FEATURE_SETS[fs or ("soft8" if soft else "hard6")]
     feat = np.empty((h, w, C), np.float32)
     mask = np.empty((h, w), np.uint8)
     pos = np.empty((h, w, 3), np.float32)
@@ -118,17 +122,17 @@ def gather(scene, fr, gbuf, sm, soft=False):
     gbuf = np.ascontiguousarray(gbuf, np.uint64)
     sm = np.ascontiguousarray(sm, np.uint32)
     rc = lib().ora_gather(_p(tris), _p(nrm), int(tris.shape[0]), _p(fv), _p(gbuf), _p(sm),
-                          w, h, int(bool(soft)), _p(feat), _p(mask), _p(pos), _p(aux))
+                          w, h, code, _p(feat), _p(mask), _p(pos), _p(aux))
     if rc:
         raise RuntimeError(f"ora_gather failed ({rc})")
     return {"feat": feat, "mask": mask, "pos": pos, "aux": aux}
 
 
-def build_features(scene, fr, soft=False):
+def build_features(scene, fr, soft=False, fs=None):
     """Shadow map, camera G-buffer and features for one frame (the oracle pipeline)."""
     sm, sm_stats = raster(scene.tris, fr.m_light, fr.sm_size, fr.sm_size, "depth")
     gb, gb_stats = raster(scene.tris, fr.m_cam, fr.width, fr.height, "key")
-    out = gather(scene, fr, gb, sm, soft=soft)
+    out = gather(scene, fr, gb, sm, soft=soft, fs=fs)
     out.update(sm=sm, gbuf=gb, sm_stats=sm_stats, gbuf_stats=gb_stats)
     return out
 

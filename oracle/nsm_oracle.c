@@ -174,10 +174,14 @@ static float lin_depth(float q, float nl, float fl) {
 }
 
 int ora_gather(const float *tris, const float *normals, int n_tris, const float *fp,
-               const uint64_t *gbuf, const uint32_t *sm, int w, int h, int soft,
+               const uint64_t *gbuf, const uint32_t *sm, int w, int h, int fs,
                float *feat, uint8_t *mask, float *pos, float *aux) {
     if (!tris || !normals || !fp || !gbuf || !sm || !feat || w <= 0 || h <= 0) return 1;
-    const int C = soft ? 8 : 6;
+    /* fs: 0 = [d/f_C, n, (z - z_f)/f_L, z/f_L]; 1 = that + [r_e/0.2, z_blk/f_L];
+     * 2 = [c_e + r_e/0.0625, z/z_f, (z - z_f)/f_L, c_c/d] (the paper's selected set,
+     * emitter size as a DC offset on c_e on a 0..4 scale) */
+    const int soft = fs == 1;
+    const int C = fs == 1 ? 8 : (fs == 2 ? 4 : 6);
     const float *ml = fp + 0, *L = fp + 16;
     const float r_e = fp[19], nl = fp[20], fl = fp[21], tanl = fp[22];
     const int S = (int)fp[23];
@@ -257,12 +261,24 @@ int ora_gather(const float *tris, const float *normals, int n_tris, const float 
             float tq = sn / fmaxf(cl, 1e-3f);
             float beta = (zf * tau) * (1.0f + 1.5f * fminf(tq, 10.0f));
             if (mask) mask[p] = (uint8_t)(inside && zf > z + beta);
-            f[0] = dv / fc;
-            f[1] = n[0];
-            f[2] = n[1];
-            f[3] = n[2];
-            f[4] = (z - zf) / fl;
-            f[5] = z / fl;
+            if (fs == 2) {
+                float vv = vx * vx + vy * vy;
+                vv = vv + vz * vz;
+                float cc = n[0] * vx + n[1] * vy;      /* cosine with the view direction */
+                cc = cc + n[2] * vz;
+                cc = cc / sqrtf(vv);
+                f[0] = cl + r_e / 0.0625f;
+                f[1] = z / zf;
+                f[2] = (z - zf) / fl;
+                f[3] = cc / dv;
+            } else {
+                f[0] = dv / fc;
+                f[1] = n[0];
+                f[2] = n[1];
+                f[3] = n[2];
+                f[4] = (z - zf) / fl;
+                f[5] = z / fl;
+            }
             if (soft) {
                 float zb = zf;
                 if (inside) {

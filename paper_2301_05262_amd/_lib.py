@@ -15,7 +15,9 @@ NSM_OK = 0
 STATUS_NAMES = {0: "NSM_OK", 1: "NSM_E_INVALID_ARG", 2: "NSM_E_SHAPE", 3: "NSM_E_UNSUPPORTED",
                 4: "NSM_E_WORKSPACE", 5: "NSM_E_NO_WEIGHTS", 6: "NSM_E_DEVICE", 7: "NSM_E_LAUNCH"}
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
-FEATURE_SETS = {"hard6": 0, "soft8": 1}
+FEATURE_SETS = {"hard6": 0, "soft8": 1, "paper4": 2}
+FEATURE_CHANNELS = {"hard6": 6, "soft8": 8, "paper4": 4}
+ARCHS = {"unet": 0, "paper": 1}
 
 EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
@@ -31,7 +33,8 @@ class NsmError(RuntimeError):
 
 
 class NetDesc(ctypes.Structure):
-    _fields_ = [("c_in", ctypes.c_int32), ("levels", ctypes.c_int32), ("widths", ctypes.c_int32 * 4)]
+    _fields_ = [("arch", ctypes.c_int32), ("c_in", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("widths", ctypes.c_int32 * 8)]
 
 
 class FrameParams(ctypes.Structure):
@@ -155,8 +158,9 @@ def nsm_build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_ou
            "nsm_build_features")
 
 
-def nsm_create(c_in, widths, dtype="f32"):
+def nsm_create(c_in, widths, dtype="f32", arch="unet"):
     d = NetDesc()
+    d.arch = ARCHS.get(arch, arch)
     d.c_in = c_in
     d.levels = len(widths)
     for i, v in enumerate(widths):

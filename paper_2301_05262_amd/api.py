@@ -32,10 +32,13 @@ class FeatureBuilder:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def __call__(self, fr, soft=False, out=None, stream=None):
-        """Returns dict(feat [H,W,C] f32, mask [H,W] u8, sm [S,S] i32 bits, gbuf [H,W] i64 keys)."""
+    def __call__(self, fr, soft=False, out=None, stream=None, fs=None):
+        """Returns dict(feat [H,W,C] f32, mask [H,W] u8, sm [S,S] i32 bits, gbuf [H,W] i64 keys).
+
+        fs: 'hard6', 'soft8' or 'paper4' (default: 'soft8' if soft else 'hard6')."""
+        fs = fs or ("soft8" if soft else "hard6")
         h, w, S = fr.height, fr.width, fr.sm_size
-        C = 8 if soft else 6
+        C = _lib.FEATURE_CHANNELS[fs]
         if out is None:
             out = {
                 "feat": torch.empty((h, w, C), dtype=torch.float32, device=self.device),
@@ -45,7 +48,7 @@ class FeatureBuilder:
             }
         ws = self.workspace(h, w, S)
         _lib.nsm_build_features(self.tris, self.normals, self.n_tris, fr, h, w,
-                                "soft8" if soft else "hard6", None, out["gbuf"], out["sm"],
+                                fs, None, out["gbuf"], out["sm"],
                                 out["feat"], out["mask"], ws, ws.numel(), stream)
         return out
 
@@ -53,10 +56,11 @@ class FeatureBuilder:
 class ShadowNet:
     """A network context (descriptor + dtype) with its device weights."""
 
-    def __init__(self, c_in, widths, dtype="f32", device=None):
+    def __init__(self, c_in, widths, dtype="f32", device=None, arch="unet"):
         self.device = _dev(device)
         self.c_in, self.widths, self.dtype = int(c_in), tuple(int(v) for v in widths), dtype
-        self.ctx = _lib.nsm_create(self.c_in, self.widths, dtype)
+        self.arch = arch
+        self.ctx = _lib.nsm_create(self.c_in, self.widths, dtype, arch)
         self.n_params = _lib.nsm_param_count(self.ctx)
         self._ws = None
         self._w = None

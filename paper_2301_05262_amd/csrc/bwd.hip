@@ -178,6 +178,7 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     constexpr int CST = G::CST, FPW = G::FPW, NFCO = G::NFCO;
     __shared__ __attribute__((aligned(16))) float xt[NPIX * CST];
     __shared__ __attribute__((aligned(16))) float dzt[TPX * CO];
+    __shared__ __attribute__((aligned(16))) float lowt[LowTile<Dt::F32, CU, TH>::SIZE];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
         const int n = (int)(t / ((long long)tiles_x * tiles_y));
         const int x0 = tx * kTW, y0 = ty * TH;
         __syncthreads();
-        load_halo_tile<Dt::F32, (CS % 4 != 0), CS, CU, CST, TH>(xt, a.in, a.low, n, a.h, a.w, x0, y0);
+        load_halo_tile<Dt::F32, (CS % 4 != 0), CS, CU, CST, TH>(xt, lowt, a.in, a.low, n, a.h, a.w, x0, y0);
         for (int idx = threadIdx.x; idx < TPX * (CO / 4); idx += 256) {
             const int px = idx / (CO / 4), c4 = idx - px * (CO / 4);
             const int y = y0 + px / kTW, x = x0 + (px % kTW);

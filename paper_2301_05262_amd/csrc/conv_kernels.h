@@ -126,6 +126,15 @@ __device__ __forceinline__ void unpack_block(const u32x4& r, float* v) {
     for (int e = 0; e < EPB; ++e) v[e] = to_f(t[e]);
 }
 
+// Low-res source tile of the upsampled channels: rows/cols y0/2-1 .. y0/2+TH/2
+// (x likewise), each clamped to the low-res image, LCST elements per pixel.
+template <Dt D, int CU, int TH>
+struct LowTile {
+    static constexpr int LH = TH / 2 + 2, LW = kTW / 2 + 2;
+    static constexpr int LCST = CU > 0 ? lds_stride<D>(CU) : 1;
+    static constexpr int SIZE = CU > 0 ? LH * LW * LCST : 1;
+};
+
 // Halo tile (TH+2) x (kTW+2) pixels of the stage input -> LDS, in the storage
 // dtype, CST elements per pixel: channels [0, CS) from `in` ([n][h][w][CS],
 // float32 when IN_F32, zero-padded up to a whole block), channels
@@ -133,55 +142,98 @@ __device__ __forceinline__ void unpack_block(const u32x4& r, float* v) {
 // source row s = (y + 0.5)/2 - 0.5, taps floor(s) (weight 0.25 for even y,
 // 0.75 for odd y) and floor(s) + 1, both clamped to the low-res image; the
 // same along x.  Pixels outside the image are zero (the conv's padding).
-template <Dt D, bool IN_F32, int CS, int CU, int CST, int TH>
-__device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, const void* in, const void* low,
-                                               int n, int h, int w, int x0, int y0) {
+// The low-res source rows are first staged in `lowt` (each read once from
+// global memory), then every upsampled value is formed from LDS.  Ends with
+// a barrier: the tile is ready when it returns.
+// With SUM the upsampled channels are added to channels [0, CU) of `in`
+// (CU == CS) instead of being appended: the skip merge by algebraic sum.
+template <Dt D, bool IN_F32, int CS, int CU, int CST, int TH, bool SUM = false>
+__device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename DT<D>::T* lowt,
+                                               const void* in, const void* low, int n, int h, int w,
+                                               int x0, int y0) {
     using T = typename DT<D>::T;
+    using LT = LowTile<D, CU, TH>;
     constexpr int EPB = DT<D>::EPB;
     constexpr int CSP = round_up(CS, EPB);
+    static_assert(!SUM || CS == CU, "a sum skip needs equal channel counts");
     constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
-    constexpr int NCH_S = CSP / EPB, NCH_U = CU / EPB, NCH = NCH_S + NCH_U;
-    for (int idx = threadIdx.x; idx < NPIX * NCH; idx += kThreads) {
-        const int pix = idx / NCH, ch = idx - pix * NCH;
+    constexpr int NCH_S = CSP / EPB, NCH_U = CU / EPB;
+    // phase 1: same-resolution channels, and the low-res source rows
+    if constexpr (NCH_S > 0)
+    for (int idx = threadIdx.x; idx < NPIX * NCH_S; idx += kThreads) {
+        const int pix = idx / NCH_S, ch = idx - pix * NCH_S;
         const int ty = pix / WP, tx = pix - ty * WP;
         const int y = y0 + ty - 1, x = x0 + tx - 1;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (y >= 0 && y < h && x >= 0 && x < w) {
-            if (ch < NCH_S) {
-                const size_t p = ((size_t)n * h + y) * w + x;
-                if constexpr (IN_F32) {
-                    const float* src = reinterpret_cast<const float*>(in) + p * CS;
-                    float f[EPB];
+            const size_t p = ((size_t)n * h + y) * w + x;
+            if constexpr (IN_F32) {
+                const float* src = reinterpret_cast<const float*>(in) + p * CS;
+                float f[EPB];
 #pragma unroll
-                    for (int e = 0; e < EPB; ++e) {
-                        const int c = ch * EPB + e;
-                        f[e] = (c < CS) ? src[c] : 0.0f;
-                    }
-                    v = pack_block<D>(f);
-                } else {
-                    v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(in) + p * CS + ch * EPB);
+                for (int e = 0; e < EPB; ++e) {
+                    const int c = ch * EPB + e;
+                    f[e] = (c < CS) ? src[c] : 0.0f;
                 }
-            } else if constexpr (CU > 0) {
-                const int hl = h >> 1, wl = w >> 1;
-                const int ya = (y - 1) >> 1, xa = (x - 1) >> 1;
-                const float wy0 = (y & 1) ? 0.75f : 0.25f, wx0 = (x & 1) ? 0.75f : 0.25f;
-                const float wy1 = 1.0f - wy0, wx1 = 1.0f - wx0;
-                const int yA = max(ya, 0), yB = min(ya + 1, hl - 1);
-                const int xA = max(xa, 0), xB = min(xa + 1, wl - 1);
-                const T* lo = reinterpret_cast<const T*>(low) + (size_t)n * hl * wl * CU + (ch - NCH_S) * EPB;
-                float f00[EPB], f01[EPB], f10[EPB], f11[EPB], f[EPB];
-                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yA * wl + xA) * CU), f00);
-                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yA * wl + xB) * CU), f01);
-                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yB * wl + xA) * CU), f10);
-                unpack_block<D>(*reinterpret_cast<const u32x4*>(lo + ((size_t)yB * wl + xB) * CU), f11);
-#pragma unroll
-                for (int e = 0; e < EPB; ++e)
-                    f[e] = wy0 * (wx0 * f00[e] + wx1 * f01[e]) + wy1 * (wx0 * f10[e] + wx1 * f11[e]);
                 v = pack_block<D>(f);
+            } else {
+                v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(in) + p * CS + ch * EPB);
             }
         }
         *reinterpret_cast<u32x4*>(&tile[pix * CST + ch * EPB]) = v;
     }
+    if constexpr (CU > 0) {
+        const int hl = h >> 1, wl = w >> 1;
+        const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
+        const T* lo = reinterpret_cast<const T*>(low) + (size_t)n * hl * wl * CU;
+        for (int idx = threadIdx.x; idx < LT::LH * LT::LW * NCH_U; idx += kThreads) {
+            const int pix = idx / NCH_U, ch = idx - pix * NCH_U;
+            const int r = pix / LT::LW, c = pix - r * LT::LW;
+            const int gy = min(max(ly0 + r, 0), hl - 1), gx = min(max(lx0 + c, 0), wl - 1);
+            *reinterpret_cast<u32x4*>(&lowt[pix * LT::LCST + ch * EPB]) =
+                *reinterpret_cast<const u32x4*>(lo + ((size_t)gy * wl + gx) * CU + ch * EPB);
+        }
+        __syncthreads();
+        // phase 2: upsampled channels from the staged rows
+        for (int idx = threadIdx.x; idx < NPIX * NCH_U; idx += kThreads) {
+            const int pix = idx / NCH_U, ch = idx - pix * NCH_U;
+            const int ty = pix / WP, tx = pix - ty * WP;
+            const int y = y0 + ty - 1, x = x0 + tx - 1;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (y >= 0 && y < h && x >= 0 && x < w) {
+                const int ra = ((y - 1) >> 1) - ly0, ca = ((x - 1) >> 1) - lx0;
+                const float wy0 = (y & 1) ? 0.75f : 0.25f, wx0 = (x & 1) ? 0.75f : 0.25f;
+                const float wy1 = 1.0f - wy0, wx1 = 1.0f - wx0;
+                const T* l00 = &lowt[(ra * LT::LW + ca) * LT::LCST + ch * EPB];
+                float f00[EPB], f01[EPB], f10[EPB], f11[EPB], f[EPB];
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(l00), f00);
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(l00 + LT::LCST), f01);
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(l00 + LT::LW * LT::LCST), f10);
+                unpack_block<D>(*reinterpret_cast<const u32x4*>(l00 + (LT::LW + 1) * LT::LCST), f11);
+#pragma unroll
+                for (int e = 0; e < EPB; ++e)
+                    f[e] = wy0 * (wx0 * f00[e] + wx1 * f01[e]) + wy1 * (wx0 * f10[e] + wx1 * f11[e]);
+                if constexpr (SUM) {
+                    float sk[EPB];
+                    unpack_block<D>(*reinterpret_cast<const u32x4*>(&tile[pix * CST + ch * EPB]), sk);
+#pragma unroll
+                    for (int e = 0; e < EPB; ++e) f[e] = sk[e] + f[e];
+                }
+                v = pack_block<D>(f);
+            }
+            *reinterpret_cast<u32x4*>(&tile[pix * CST + (SUM ? 0 : CSP) + ch * EPB]) = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Hardware dispatches consecutive workgroups round-robin over the 8 XCDs;
+// give each XCD a contiguous run of logical tiles so that neighbouring
+// tiles (which share halo rows and low-res rows) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int total) {
+    const int xcd = b & 7, k = b >> 3;
+    const int q = total >> 3, r = total & 7;
+    return xcd * q + min(xcd, r) + k;
 }
 
 // Store four consecutive channels co..co+3 (fewer at the end of an odd-sized
@@ -217,13 +269,15 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3(ConvArgs a) {
     static_assert(MODE != OutMode::Pool || RPW == 2, "pooling needs row pairs per wave");
 
     __shared__ __attribute__((aligned(16))) T tile[NPIX * CST];
+    __shared__ __attribute__((aligned(16))) T lowt[LowTile<D, CU, TH>::SIZE];
 
     const int h = a.h, w = a.w;
-    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * TH, n = blockIdx.z;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
 
     // ---------------- prologue: halo tile to LDS
-    load_halo_tile<D, IN_F32, CS, CU, CST, TH>(tile, a.in, a.low, n, h, w, x0, y0);
-    __syncthreads();
+    load_halo_tile<D, IN_F32, CS, CU, CST, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     // ---------------- main loop
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

@@ -40,12 +40,22 @@ static_assert(sizeof(TriSetup) == 64, "TriSetup must stay 64 bytes");
 
 struct Mat4 { float m[16]; };
 
-// Workspace needed by one raster pass over n_tris triangles.
+// One rasterisation target: clear `out` (w*h texels of 4 or 8 bytes) and
+// keep the nearest fragment; key64 selects the camera key
+// (depth bits << 32 | id) instead of plain depth bits.
+struct RasterPass {
+    Mat4 m;
+    int w, h;
+    int key64;
+    void* out;
+};
+struct RasterPasses {
+    RasterPass p[2];
+    int npass;          // 1 or 2; both passes share one setup / scan / raster launch
+};
+// Workspace for up to two passes over n_tris triangles.
 size_t raster_workspace_bytes(int n_tris);
-// Clear `out` (w*h texels of 4 or 8 bytes) and rasterise; key64 selects the
-// camera key (depth bits << 32 | id) instead of plain depth bits.
-hipError_t raster(const float* tris, int n_tris, const Mat4& m, int w, int h, bool key64,
-                  void* out, void* ws, hipStream_t s);
+hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws, hipStream_t s);
 
 struct GatherParams {
     Mat4 ml;
@@ -55,7 +65,7 @@ struct GatherParams {
     float tanx, tany, fc;
 };
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
-                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, bool soft, float* feat,
+                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s);
 
 // --------------------------------------------------------------- network
@@ -92,6 +102,42 @@ struct ConvArgs {
 };
 hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs& a, hipStream_t s);
 bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32);
+
+// ---------------------------------------------- the paper's network (P-net)
+enum class PMode { Store = 0, PoolOnly = 1, PoolSkip = 2, Head = 3 };
+
+// One P-net stage: 3x3 conv (cs [+ cu] -> c1) + ReLU, 1x1 (c1 -> c2) + ReLU.
+// Input: `in` ([.., cs]) and/or up(low) ([.., cu] at half resolution), summed
+// when `sum` (cs == cu), concatenated otherwise (cs = 0: upsampled input only).
+struct PStage {
+    int cs, cu;
+    bool sum;
+    int c1, c2;
+    PMode mode;
+    bool in_f32;
+};
+
+struct PConvArgs {
+    const void* in;
+    const void* low;
+    const void* wpk;      // packed 3x3 weights
+    const float* b1;      // [c1]
+    const void* w1pk;     // packed 1x1 weights
+    const float* b2;      // [c2]
+    void* out;            // [n][h][w][c2] (Store, PoolSkip)
+    void* pooled;         // [n][h/2][w/2][c2] average-pooled (PoolOnly, PoolSkip)
+    const float* head_w;  // [c2] + bias (Head)
+    float* vis;
+    float* logits;
+    int n, h, w;
+};
+
+bool pconv_supported(const PStage& st);
+size_t pconv_packed_bytes(const PStage& st, Dt dt);
+size_t pconv_w1_offset(const PStage& st, Dt dt);
+hipError_t pconv_pack(const PStage& st, Dt dt, const float* w3, const float* w1, void* packed,
+                      hipStream_t s);
+hipError_t pconv_forward(const PStage& st, Dt dt, const PConvArgs& a, hipStream_t s);
 
 // ------------------------------------------------------ backward (float32)
 bool backward_supported(const ConvStage& st);

@@ -31,6 +31,9 @@ struct StagePlan {
     size_t b_off;       // offset (floats) of the biases
     size_t pk_off;      // byte offset of packed weights in the device buffer
     size_t pk_bwd_off;  // byte offset of the input-gradient (flipped) pack, FP32 only
+    // paper-network stages: the fused 1x1 that follows the 3x3
+    PStage ps;
+    size_t w2_off, b2_off;
 };
 
 bool device_ok() {
@@ -88,7 +91,7 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
                               void* stream) {
     if (!fp || !sm_out || !feat_out || n_tris < 0) return NSM_E_INVALID_ARG;
     if (n_tris > 0 && (!tris || !tri_normals)) return NSM_E_INVALID_ARG;
-    if (fs != NSM_FEAT_HARD6 && fs != NSM_FEAT_SOFT8) return NSM_E_INVALID_ARG;
+    if (fs != NSM_FEAT_HARD6 && fs != NSM_FEAT_SOFT8 && fs != NSM_FEAT_PAPER4) return NSM_E_INVALID_ARG;
     size_t need = 0;
     nsm_status st = nsm_features_workspace_bytes(n_tris, h, w, fp->sm_size, &need);
     if (st != NSM_OK) return st;
@@ -102,13 +105,19 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     std::memcpy(ml.m, fp->m_light, sizeof(ml.m));
     std::memcpy(mc.m, fp->m_cam, sizeof(mc.m));
     const int S = fp->sm_size;
-    if (raster(tris, n_tris, ml, S, S, false, sm_out, ws, s) != hipSuccess) return NSM_E_LAUNCH;
+    // light-view map and (unless the caller provides it) the camera G-buffer
+    // in one setup / scan / raster sequence
+    RasterPasses P{};
+    P.p[0] = RasterPass{ml, S, S, 0, sm_out};
+    P.npass = 1;
     const uint64_t* gb = gbuf_in;
     if (!gb) {
         uint64_t* target = gbuf_out ? gbuf_out : gbuf_ws;
-        if (raster(tris, n_tris, mc, w, h, true, target, ws, s) != hipSuccess) return NSM_E_LAUNCH;
+        P.p[1] = RasterPass{mc, w, h, 1, target};
+        P.npass = 2;
         gb = target;
     }
+    if (raster(tris, n_tris, P, ws, s) != hipSuccess) return NSM_E_LAUNCH;
     GatherParams gp;
     gp.ml = ml;
     for (int k = 0; k < 3; ++k) {
@@ -126,7 +135,7 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     gp.tanx = fp->cam_tan_half_x;
     gp.tany = fp->cam_tan_half_y;
     gp.fc = fp->cam_far;
-    if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, w, h, fs == NSM_FEAT_SOFT8, feat_out,
+    if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, w, h, (int)fs, feat_out,
                mask_out, s) != hipSuccess)
         return NSM_E_LAUNCH;
     return NSM_OK;
@@ -138,15 +147,64 @@ nsm_status nsm_create(const nsm_net_desc* desc, nsm_dtype dtype, nsm_ctx** out) 
     *out = nullptr;
     if (dtype != NSM_F32 && dtype != NSM_BF16 && dtype != NSM_F16) return NSM_E_INVALID_ARG;
     const int L = desc->levels;
-    if (L < 2 || L > 4 || desc->c_in < 1) return NSM_E_UNSUPPORTED;
+    if (L < 2 || L > 5 || desc->c_in < 1) return NSM_E_UNSUPPORTED;
+    if (desc->arch == NSM_ARCH_UNET && L > 4) return NSM_E_UNSUPPORTED;
     for (int l = 0; l < L; ++l)
         if (desc->widths[l] < 1) return NSM_E_UNSUPPORTED;
+    if (desc->arch != NSM_ARCH_UNET && desc->arch != NSM_ARCH_PAPER) return NSM_E_INVALID_ARG;
     nsm_ctx* c = new (std::nothrow) nsm_ctx();
     if (!c) return NSM_E_DEVICE;
     c->desc = *desc;
     c->dt = static_cast<Dt>(dtype);
     const int* wd = desc->widths;
     size_t off = 0;
+    if (desc->arch == NSM_ARCH_PAPER) {
+        if (L != 3 && L != 5) {
+            delete c;
+            return NSM_E_UNSUPPORTED;
+        }
+        auto addp = [&](const char* name, PStage ps, int level) {
+            StagePlan p{};
+            p.name = name;
+            p.ps = ps;
+            p.level = level;
+            p.w_off = off;
+            off += (size_t)ps.c1 * 9 * (ps.cs + (ps.sum ? 0 : ps.cu));
+            p.b_off = off;
+            off += ps.c1;
+            p.w2_off = off;
+            off += (size_t)ps.c2 * ps.c1;
+            p.b2_off = off;
+            off += ps.c2;
+            c->stages.push_back(p);
+        };
+        static const char* pe[] = {"E0", "E1", "E2", "E3"};
+        static const char* pd[] = {"D0", "D1", "D2", "D3"};
+        for (int l = 0; l < L - 1; ++l)
+            addp(pe[l], PStage{l == 0 ? desc->c_in : wd[l - 1], 0, false, wd[l], wd[l],
+                               l == 0 ? PMode::PoolOnly : PMode::PoolSkip, l == 0}, l);
+        addp("B", PStage{wd[L - 2], 0, false, wd[L - 1], wd[L - 2], PMode::Store, false}, L - 1);
+        for (int l = L - 2; l >= 1; --l)
+            addp(pd[l], PStage{wd[l], wd[l], true, wd[l], wd[l - 1], PMode::Store, false}, l);
+        addp("D0", PStage{0, wd[0], false, wd[0], wd[0], PMode::Head, false}, 0);
+        c->head_w_off = off;
+        off += wd[0] + 1;
+        c->n_params = off;
+        size_t pk = 0;
+        for (auto& p : c->stages) {
+            if (!pconv_supported(p.ps)) {
+                delete c;
+                return NSM_E_UNSUPPORTED;
+            }
+            p.pk_off = pk;
+            pk += align256(pconv_packed_bytes(p.ps, c->dt));
+        }
+        c->trainable = false;
+        c->flat_off = pk;
+        c->dbuf_bytes = pk + align256(c->n_params * 4);
+        *out = c;
+        return NSM_OK;
+    }
     auto add = [&](const char* name, ConvStage st, OutMode mode, bool f32, int level) {
         StagePlan p;
         p.name = name;
@@ -224,6 +282,11 @@ nsm_status nsm_set_weights(nsm_ctx* ctx, const float* w, size_t n, void* stream)
     float* flat = reinterpret_cast<float*>(base + ctx->flat_off);
     if (hipMemcpyAsync(flat, w, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return NSM_E_DEVICE;
     for (const auto& p : ctx->stages) {
+        if (ctx->desc.arch == NSM_ARCH_PAPER) {
+            if (pconv_pack(p.ps, ctx->dt, flat + p.w_off, flat + p.w2_off, base + p.pk_off, s) != hipSuccess)
+                return NSM_E_LAUNCH;
+            continue;
+        }
         if (pack_weights(p.st, ctx->dt, flat + p.w_off, base + p.pk_off, s) != hipSuccess)
             return NSM_E_LAUNCH;
         if (ctx->trainable &&
@@ -266,6 +329,70 @@ FwdLayout plan_forward(const nsm_ctx* c, int n, int h, int w, bool training) {
     L.d0act = training ? take((size_t)n * (size_t)h * w * wd[0] * 4) : 0;
     L.total = off;
     return L;
+}
+
+// Paper network: skip[l] = x_l (l >= 1), pool[l] = avgpool(x_l), dec[l] = y_l
+// (decoder output at level l >= 1, w_{l-1} channels; dec[L-1] is the bottleneck).
+FwdLayout plan_forward_paper(const nsm_ctx* c, int n, int h, int w) {
+    FwdLayout L{};
+    const int lv = c->desc.levels;
+    const int* wd = c->desc.widths;
+    const size_t es = elem_size(c->dt);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    auto px = [&](int l) { return (size_t)n * (size_t)(h >> l) * (size_t)(w >> l); };
+    for (int l = 0; l < lv - 1; ++l) {
+        if (l >= 1) L.skip[l] = take(px(l) * wd[l] * es);
+        L.pool[l] = take(px(l + 1) * wd[l] * es);
+    }
+    for (int l = 1; l <= lv - 1; ++l) L.dec[l] = take(px(l) * wd[l - 1] * es);
+    L.total = off;
+    return L;
+}
+
+hipError_t run_forward_paper(const nsm_ctx* c, const float* feat, int n, int h, int w, float* vis,
+                             float* logits, char* ws, const FwdLayout& L, hipStream_t s) {
+    const char* base = reinterpret_cast<const char*>(c->dbuf);
+    const float* flat = reinterpret_cast<const float*>(base + c->flat_off);
+    const int lv = c->desc.levels;
+    const void* prev = feat;
+    for (size_t i = 0; i < c->stages.size(); ++i) {
+        const StagePlan& p = c->stages[i];
+        const int l = p.level;
+        PConvArgs a{};
+        a.wpk = base + p.pk_off;
+        a.b1 = flat + p.b_off;
+        a.w1pk = base + p.pk_off + pconv_w1_offset(p.ps, c->dt);
+        a.b2 = flat + p.b2_off;
+        a.n = n;
+        a.h = h >> l;
+        a.w = w >> l;
+        if (p.ps.mode == PMode::PoolOnly || p.ps.mode == PMode::PoolSkip) {     // encoder
+            a.in = prev;
+            if (p.ps.mode == PMode::PoolSkip) a.out = ws + L.skip[l];
+            a.pooled = ws + L.pool[l];
+            prev = a.pooled;
+        } else if (l == lv - 1) {                                              // bottleneck
+            a.in = prev;
+            a.out = ws + L.dec[l];
+        } else if (p.ps.mode == PMode::Store) {                                // decoder, sum skip
+            a.in = ws + L.skip[l];
+            a.low = ws + L.dec[l + 1];
+            a.out = ws + L.dec[l];
+        } else {                                                               // level 0 + output
+            a.low = ws + L.dec[1];
+            a.head_w = flat + c->head_w_off;
+            a.vis = vis;
+            a.logits = logits;
+        }
+        hipError_t e = pconv_forward(p.ps, c->dt, a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 nsm_status check_net_shape(const nsm_ctx* c, int n, int h, int w) {
@@ -428,7 +555,8 @@ nsm_status nsm_workspace_bytes(const nsm_ctx* ctx, int n, int h, int w, int trai
         *bytes = plan_training(ctx, n, h, w).total;
         return NSM_OK;
     }
-    *bytes = plan_forward(ctx, n, h, w, false).total;
+    *bytes = ctx->desc.arch == NSM_ARCH_PAPER ? plan_forward_paper(ctx, n, h, w).total
+                                              : plan_forward(ctx, n, h, w, false).total;
     return NSM_OK;
 }
 
@@ -438,13 +566,15 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
     nsm_status st = check_net_shape(ctx, n, h, w);
     if (st != NSM_OK) return st;
     if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
-    FwdLayout L = plan_forward(ctx, n, h, w, false);
+    const bool paper = ctx->desc.arch == NSM_ARCH_PAPER;
+    FwdLayout L = paper ? plan_forward_paper(ctx, n, h, w) : plan_forward(ctx, n, h, w, false);
     if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (run_forward(ctx, feat, n, h, w, vis_out, logits_out, reinterpret_cast<char*>(workspace), L,
-                    nullptr, s) != hipSuccess)
-        return NSM_E_LAUNCH;
+    char* ws = reinterpret_cast<char*>(workspace);
+    const hipError_t e = paper ? run_forward_paper(ctx, feat, n, h, w, vis_out, logits_out, ws, L, s)
+                               : run_forward(ctx, feat, n, h, w, vis_out, logits_out, ws, L, nullptr, s);
+    if (e != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
 }
 

@@ -1,0 +1,337 @@
+// Stages of the paper's own network (Sec. 4.5): per level one 3x3 conv and
+// one 1x1 conv (each + ReLU), average pooling, skip merged by a sum, no
+// level-0 skip, a 1x1 output conv and a sigmoid.
+//
+// One kernel per stage: halo tile -> LDS (with the sum skip
+// up(y_{l+1}) + x_l formed in the prologue), the 3x3 as MFMA implicit GEMM
+// (as in conv_kernels.h), then the 1x1 as a second MFMA GEMM taken straight
+// from the accumulator registers: a 16x16 accumulator holds, per lane, four
+// consecutive output channels of one pixel, which is exactly the B-operand
+// layout of v_mfma_f32_16x16x16_{bf16,f16} (K = 16 channels per MFMA), and
+// per-element for v_mfma_f32_16x16x4_f32.  Nothing of the 3x3 output
+// touches memory.  Epilogues: store; 2x2 average pool (with or without the
+// full-resolution skip store); the output 1x1 + sigmoid.
+#include <hip/hip_runtime.h>
+
+#include "conv_kernels.h"
+
+namespace nsm {
+namespace {
+using namespace ck;
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+template <Dt D>
+__device__ __forceinline__ f32x4 mfma_1x1(const uint2& wa, const f32x4& act, f32x4 acc) {
+    using T = typename DT<D>::T;
+    if constexpr (D == Dt::F32) {
+        (void)wa;
+        return acc;   // float32 path handled per element by the caller
+    } else {
+        T b4[4] = {from_f<T>(act[0]), from_f<T>(act[1]), from_f<T>(act[2]), from_f<T>(act[3])};
+        if constexpr (D == Dt::BF16) {
+            bf16x4 a, b;
+            __builtin_memcpy(&a, &wa, 8);
+            __builtin_memcpy(&b, b4, 8);
+            return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        } else {
+            f16x4 a, b;
+            __builtin_memcpy(&a, &wa, 8);
+            __builtin_memcpy(&b, b4, 8);
+            return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+        }
+    }
+}
+
+template <Dt D, bool IN_F32, int CS, int CU, bool SUM, int C1, int C2, PMode MODE, int TH>
+__global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
+    using T = typename DT<D>::T;
+    using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
+    constexpr int EPB = G::EPB, CST = G::CST, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
+    constexpr int NF2 = (C2 + 15) / 16;
+    constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
+    constexpr int RPW = TH / 4, MF = RPW * 2;
+    constexpr bool POOL = MODE == PMode::PoolOnly || MODE == PMode::PoolSkip;
+    static_assert(!POOL || RPW == 2, "pooling needs row pairs per wave");
+    static_assert(C1 % 16 == 0, "the 1x1 reads whole 16-channel fragments");
+
+    __shared__ __attribute__((aligned(16))) T tile[NPIX * CST];
+    __shared__ __attribute__((aligned(16))) T lowt[LowTile<D, CU, TH>::SIZE];
+
+    const int h = a.h, w = a.w;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
+
+    load_halo_tile<D, IN_F32, CS, CU, CST, TH, SUM>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = lane & 15, g = lane >> 4;
+    const u32x4* wpk = reinterpret_cast<const u32x4*>(a.wpk);
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int q = 0; q < NKG; ++q) {
+        u32x4 wf[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) wf[f] = wpk[(f * NKG + q) * 64 + lane];
+        int b = 4 * q + g;
+        if (b >= NB) b = NB - 1;
+        const int tap = b / BPT, cb = b - tap * BPT;
+        const int ky = tap / 3, kx = tap - ky * 3;
+        const int base = (ky * WP + kx + px) * CST + cb * EPB;
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const int r = wave * RPW + (m >> 1), cf = m & 1;
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + (r * WP + cf * 16) * CST]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[m][f] = mfma_kgroup<D>(wf[f], xb, acc[m][f]);
+        }
+    }
+    // 3x3 bias + ReLU
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        float bb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bb[e] = a.b1[f * 16 + 4 * g + e];
+#pragma unroll
+        for (int m = 0; m < MF; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[m][f][e] = fmaxf(acc[m][f][e] + bb[e], 0.0f);
+    }
+    // 1x1 on the accumulators: acc2[co2][px] = sum_co1 W1[co2][co1] * acc[co1][px]
+    f32x4 acc2[MF][NF2];
+#pragma unroll
+    for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f2 = 0; f2 < NF2; ++f2) acc2[m][f2] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int f2 = 0; f2 < NF2; ++f2) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if constexpr (D == Dt::F32) {
+                const f32x4 w4 = reinterpret_cast<const f32x4*>(a.w1pk)[(f2 * NF + f) * 64 + lane];
+#pragma unroll
+                for (int m = 0; m < MF; ++m)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc2[m][f2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[e], acc[m][f][e], acc2[m][f2], 0, 0, 0);
+            } else {
+                const uint2 w4 = reinterpret_cast<const uint2*>(a.w1pk)[(f2 * NF + f) * 64 + lane];
+#pragma unroll
+                for (int m = 0; m < MF; ++m) acc2[m][f2] = mfma_1x1<D>(w4, acc[m][f], acc2[m][f2]);
+            }
+        }
+    }
+#pragma unroll
+    for (int f2 = 0; f2 < NF2; ++f2) {
+        float bb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int co = f2 * 16 + 4 * g + e;
+            bb[e] = co < C2 ? a.b2[co] : 0.0f;
+        }
+#pragma unroll
+        for (int m = 0; m < MF; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc2[m][f2][e] = fmaxf(acc2[m][f2][e] + bb[e], 0.0f);
+    }
+
+    if constexpr (MODE == PMode::Head) {
+        float hw[NF2][4];
+#pragma unroll
+        for (int f2 = 0; f2 < NF2; ++f2)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = f2 * 16 + 4 * g + e;
+                hw[f2][e] = co < C2 ? a.head_w[co] : 0.0f;
+            }
+        const float hb = a.head_w[C2];
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
+            float s = 0.0f;
+#pragma unroll
+            for (int f2 = 0; f2 < NF2; ++f2)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s += hw[f2][e] * acc2[m][f2][e];
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (y < h && x < w && g == 0) {
+                const size_t p = ((size_t)n * h + y) * w + x;
+                const float logit = s + hb;
+                a.vis[p] = 1.0f / (1.0f + __expf(-logit));
+                if (a.logits) a.logits[p] = logit;
+            }
+        }
+    } else {
+        if constexpr (MODE != PMode::PoolOnly) {
+            T* out = reinterpret_cast<T*>(a.out);
+#pragma unroll
+            for (int m = 0; m < MF; ++m) {
+                const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
+                if (y < h && x < w) {
+                    const size_t p = ((size_t)n * h + y) * w + x;
+#pragma unroll
+                    for (int f2 = 0; f2 < NF2; ++f2) {
+                        const int co = f2 * 16 + 4 * g;
+                        if (co < C2) {
+                            float v4[4] = {acc2[m][f2][0], acc2[m][f2][1], acc2[m][f2][2], acc2[m][f2][3]};
+                            store4<T, C2>(out + p * C2 + co, co, v4);
+                        }
+                    }
+                }
+            }
+        }
+        if constexpr (POOL) {
+            T* pooled = reinterpret_cast<T*>(a.pooled);
+            const int hp = h >> 1, wp = w >> 1;
+#pragma unroll
+            for (int cf = 0; cf < 2; ++cf) {
+                const int yp = (y0 >> 1) + wave, xp = ((x0 + cf * 16 + px) >> 1);
+#pragma unroll
+                for (int f2 = 0; f2 < NF2; ++f2) {
+                    float av[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float v = acc2[cf][f2][e] + acc2[2 + cf][f2][e];
+                        av[e] = (v + __shfl_xor(v, 1)) * 0.25f;
+                    }
+                    const int co = f2 * 16 + 4 * g;
+                    if ((px & 1) == 0 && yp < hp && xp < wp && co < C2) {
+                        const size_t p = ((size_t)n * hp + yp) * wp + xp;
+                        store4<T, C2>(pooled + p * C2 + co, co, av);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// 1x1 weights [C2][C1] float32 -> [NF2][NF1][64 lanes][4] storage type:
+// lane (co2 = l % 16, g = l / 16) element e holds W1[16 f2 + co2][16 f + 4 g + e].
+template <Dt D, int C1, int C2>
+__global__ void k_pack1x1(const float* __restrict__ w, void* __restrict__ out) {
+    using T = typename DT<D>::T;
+    constexpr int NF1 = C1 / 16, NF2 = (C2 + 15) / 16;
+    constexpr int total = NF2 * NF1 * 64 * 4;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int e = idx & 3, lane = (idx >> 2) & 63, f = (idx >> 8) % NF1, f2 = (idx >> 8) / NF1;
+    const int co2 = f2 * 16 + (lane & 15), co1 = f * 16 + 4 * (lane >> 4) + e;
+    const float v = (co2 < C2) ? w[(size_t)co2 * C1 + co1] : 0.0f;
+    reinterpret_cast<T*>(out)[idx] = from_f<T>(v);
+}
+
+// (cs, cu, sum, c1, c2, mode, float32 input, tile rows)
+#define NSM_PSTAGES(X)                                 \
+    X(4, 0, false, 16, 16, PoolOnly, true, 8)          \
+    X(16, 0, false, 32, 32, PoolSkip, false, 8)        \
+    X(32, 0, false, 64, 64, PoolSkip, false, 8)        \
+    X(64, 0, false, 128, 128, PoolSkip, false, 8)      \
+    X(128, 0, false, 256, 128, Store, false, 4)        \
+    X(32, 0, false, 64, 32, Store, false, 8)           \
+    X(128, 128, true, 128, 64, Store, false, 4)        \
+    X(64, 64, true, 64, 32, Store, false, 8)           \
+    X(32, 32, true, 32, 16, Store, false, 8)           \
+    X(0, 16, false, 16, 16, Head, false, 8)
+
+template <Dt D> constexpr const char* pdt_suffix() {
+    return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : " f16");
+}
+
+#define NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)                                        \
+    (st.cs == CS_ && st.cu == CU_ && st.sum == SUM_ && st.c1 == C1_ && st.c2 == C2_ &&          \
+     st.mode == PMode::MODE_ && st.in_f32 == F32_)
+
+template <Dt D>
+hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* found) {
+#define NSM_PCASE(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_)                                     \
+    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)) {                                      \
+        *found = true;                                                                            \
+        dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH_ - 1) / TH_, a.n);                             \
+        TraceScope ts("pconv " #CS_ "+" #CU_ "->" #C1_ "->" #C2_ " " #MODE_, pdt_suffix<D>(), s); \
+        k_pconv<D, F32_, CS_, CU_, SUM_, C1_, C2_, PMode::MODE_, TH_><<<grid, kThreads, 0, s>>>(a); \
+        return hipGetLastError();                                                                 \
+    }
+    NSM_PSTAGES(NSM_PCASE)
+#undef NSM_PCASE
+    *found = false;
+    return hipErrorInvalidValue;
+}
+
+template <Dt D>
+bool ppack(const PStage& st, const float* w3, const float* w1, void* out, hipStream_t s, size_t* bytes) {
+#define NSM_PPACK(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_)                                     \
+    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)) {                                      \
+        constexpr size_t b3 = packed_bytes<D, CS_, (SUM_ ? 0 : CU_), C1_>();                      \
+        constexpr size_t b1 = (size_t)((C2_ + 15) / 16) * (C1_ / 16) * 64 * 4 * sizeof(typename DT<D>::T); \
+        if (bytes) *bytes = ((b3 + 255) & ~(size_t)255) + b1;                                     \
+        if (out) {                                                                                \
+            constexpr int n3 = (int)(b3 / 16 * DT<D>::EPB);                                       \
+            k_pack<D, CS_, (SUM_ ? 0 : CU_), C1_><<<(n3 + 255) / 256, 256, 0, s>>>(w3, out);      \
+            constexpr int n1 = (int)(b1 / sizeof(typename DT<D>::T));                             \
+            k_pack1x1<D, C1_, C2_><<<(n1 + 255) / 256, 256, 0, s>>>(                              \
+                w1, reinterpret_cast<char*>(out) + ((b3 + 255) & ~(size_t)255));                  \
+        }                                                                                         \
+        return true;                                                                              \
+    }
+    NSM_PSTAGES(NSM_PPACK)
+#undef NSM_PPACK
+    return false;
+}
+
+}  // namespace
+
+bool pconv_supported(const PStage& st) {
+#define NSM_PSUP(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_) \
+    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)) return true;
+    NSM_PSTAGES(NSM_PSUP)
+#undef NSM_PSUP
+    return false;
+}
+
+size_t pconv_packed_bytes(const PStage& st, Dt dt) {
+    size_t b = 0;
+    switch (dt) {
+        case Dt::F32: ppack<Dt::F32>(st, nullptr, nullptr, nullptr, nullptr, &b); break;
+        case Dt::BF16: ppack<Dt::BF16>(st, nullptr, nullptr, nullptr, nullptr, &b); break;
+        case Dt::F16: ppack<Dt::F16>(st, nullptr, nullptr, nullptr, nullptr, &b); break;
+    }
+    return b;
+}
+
+hipError_t pconv_pack(const PStage& st, Dt dt, const float* w3, const float* w1, void* packed,
+                      hipStream_t s) {
+    bool ok = false;
+    switch (dt) {
+        case Dt::F32: ok = ppack<Dt::F32>(st, w3, w1, packed, s, nullptr); break;
+        case Dt::BF16: ok = ppack<Dt::BF16>(st, w3, w1, packed, s, nullptr); break;
+        case Dt::F16: ok = ppack<Dt::F16>(st, w3, w1, packed, s, nullptr); break;
+    }
+    return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+size_t pconv_w1_offset(const PStage& st, Dt dt) {
+    // the 1x1 pack follows the 256-byte aligned 3x3 pack
+    const int NF2 = (st.c2 + 15) / 16, NF1 = st.c1 / 16;
+    const size_t b1 = (size_t)NF2 * NF1 * 64 * 4 * (dt == Dt::F32 ? 4 : 2);
+    return pconv_packed_bytes(st, dt) - b1;
+}
+
+hipError_t pconv_forward(const PStage& st, Dt dt, const PConvArgs& a, hipStream_t s) {
+    bool found = false;
+    hipError_t e = hipErrorInvalidValue;
+    switch (dt) {
+        case Dt::F32: e = plaunch<Dt::F32>(st, a, s, &found); break;
+        case Dt::BF16: e = plaunch<Dt::BF16>(st, a, s, &found); break;
+        case Dt::F16: e = plaunch<Dt::F16>(st, a, s, &found); break;
+    }
+    return found ? e : hipErrorInvalidValue;
+}
+
+}  // namespace nsm

@@ -46,22 +46,38 @@ __device__ __forceinline__ int64_t floor_div256(int64_t a) {
     return (a >= 0) ? (a >> 8) : -((-a + 255) >> 8);
 }
 
-__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) p[i] = v;
+// Clear up to two targets with 16-byte stores (a 4-byte tail loop covers
+// sizes that are not multiples of 16 bytes).
+struct FillJob {
+    void* p;
+    size_t bytes;
+    unsigned long long pattern;   // 8-byte pattern repeated
+};
+
+__global__ void __launch_bounds__(256) k_fill2(FillJob a, FillJob b) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const FillJob f = j ? b : a;
+        if (!f.p) continue;
+        const size_t n16 = f.bytes / 16;
+        uint4 v;
+        v.x = v.z = (uint32_t)(f.pattern & 0xFFFFFFFFull);
+        v.y = v.w = (uint32_t)(f.pattern >> 32);
+        uint4* q = reinterpret_cast<uint4*>(f.p);
+        for (size_t i = tid; i < n16; i += stride) q[i] = v;
+        // tail (fewer than 16 bytes, 4-byte aligned)
+        uint32_t* t32 = reinterpret_cast<uint32_t*>(f.p);
+        for (size_t i = n16 * 4 + tid; i < f.bytes / 4; i += stride)
+            t32[i] = (i & 1) ? (uint32_t)(f.pattern >> 32) : (uint32_t)(f.pattern & 0xFFFFFFFFull);
+    }
 }
 
-__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) p[i] = v;
-}
-
-__global__ void k_tri_setup(const float* __restrict__ tris, int n_tris, Mat4 M, int w, int h,
-                            TriSetup* __restrict__ setup, int* __restrict__ counts) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tris) return;
+// Snap one triangle, order it counter-clockwise and count the 8x8 tiles of
+// its texel bounding box (0 if dropped, degenerate or off-screen).
+__device__ __forceinline__ int tri_setup_one(const float* __restrict__ tris, int t, const Mat4& M,
+                                             int w, int h, TriSetup* __restrict__ setup) {
     const float* T = tris + 9 * (size_t)t;
     const float fw = (float)w, fh = (float)h;
     int64_t X[3], Y[3];
@@ -125,66 +141,122 @@ __global__ void k_tri_setup(const float* __restrict__ tris, int n_tris, Mat4 M, 
         for (int v = 0; v < 3; ++v) { s.x[v] = 0; s.y[v] = 0; s.z[v] = 0.0f; }
     }
     setup[t] = s;
-    counts[t] = count;
+    return count;
 }
 
-// Exclusive scan of counts[0..n) into offsets[0..n] (offsets[n] = total), one block.
-__global__ void __launch_bounds__(kScanThreads) k_scan(const int* __restrict__ counts, int n,
-                                                       long long* __restrict__ offsets) {
-    __shared__ long long part[kScanThreads];
-    int tid = threadIdx.x;
-    int chunk = (n + kScanThreads - 1) / kScanThreads;
-    int b = tid * chunk, e = min(n, b + chunk);
-    long long sum = 0;
-    for (int i = b; i < e; ++i) sum += counts[i];
-    part[tid] = sum;
+// Block-local exclusive scan of one int per thread (256 threads); returns the
+// thread's offset and writes the block total to *total (all threads call it).
+__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(incl, d);
+        if (lane >= d) incl += u;
+    }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {   // Hillis-Steele inclusive scan
-        long long v = (tid >= off) ? part[tid - off] : 0;
+    int off = 0;
+    for (int k = 0; k < wave; ++k) off += wsum[k];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    return off + incl - v;
+}
+
+__global__ void __launch_bounds__(256) k_tri_setup(const float* __restrict__ tris, int n_tris,
+                                                   RasterPasses P, TriSetup* __restrict__ setup,
+                                                   int* __restrict__ local_off, int* __restrict__ block_sum) {
+    // virtual triangle v = pass * n_tris + t
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    int count = 0;
+    if (v < P.npass * n_tris) {
+        const int pass = v >= n_tris ? 1 : 0;
+        const RasterPass& rp = pass ? P.p[1] : P.p[0];
+        count = tri_setup_one(tris, v - pass * n_tris, rp.m, rp.w, rp.h, setup + pass * n_tris);
+    }
+    int total;
+    const int off = block_exclusive_scan(count, &total);
+    if (v < P.npass * n_tris) local_off[v] = off;
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
+}
+
+// Scan of the per-block tile totals written by k_tri_setup into block bases
+// (base[b] = sum of totals of blocks < b, base[nblk] = all tiles); one block,
+// coalesced loads, wave-level scans.
+__global__ void __launch_bounds__(kScanThreads) k_block_scan(const int* __restrict__ block_sum, int nblk,
+                                                             long long* __restrict__ base) {
+    __shared__ long long wsum[kScanThreads / 64];
+    __shared__ long long carry;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int seg = 0; seg < nblk; seg += kScanThreads) {
+        const int i = seg + tid;
+        const long long v = (i < nblk) ? block_sum[i] : 0;
+        long long incl = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const long long u = __shfl_up(incl, d);
+            if (lane >= d) incl += u;
+        }
+        if (lane == 63) wsum[wave] = incl;
         __syncthreads();
-        part[tid] += v;
+        long long woff = carry;
+        for (int k = 0; k < wave; ++k) woff += wsum[k];
+        if (i < nblk) base[i] = woff + incl - v;
+        __syncthreads();
+        if (tid == kScanThreads - 1) carry = woff + incl;
         __syncthreads();
     }
-    long long run = part[tid] - sum;
-    for (int i = b; i < e; ++i) {
-        offsets[i] = run;
-        run += counts[i];
-    }
-    if (tid == kScanThreads - 1) offsets[n] = part[tid];
+    if (tid == 0) base[nblk] = carry;
+}
+
+// First tile item of triangle t (t == n gives the total).
+__device__ __forceinline__ long long tri_start(const long long* __restrict__ base,
+                                               const int* __restrict__ local_off, int t, int n) {
+    return (t >= n) ? base[(n + 255) >> 8] : base[t >> 8] + local_off[t];
 }
 
 __device__ __forceinline__ bool edge_inclusive(int64_t dx, int64_t dy) {
     return dy > 0 || (dy == 0 && dx < 0);
 }
 
-template <bool KEY64>
 __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ setup,
-                                                const long long* __restrict__ offsets, int n_tris,
-                                                int w, int h, void* __restrict__ out) {
+                                                const long long* __restrict__ base,
+                                                const int* __restrict__ local_off, int n_tris,
+                                                RasterPasses P) {
     const int lane = threadIdx.x & 63;
+    const int nv = P.npass * n_tris;             // virtual triangles
     const long long wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const long long nwaves = gridDim.x * (blockDim.x >> 6);
-    const long long total = offsets[n_tris];
+    const long long total = tri_start(base, local_off, nv, nv);
     const long long per = (total + nwaves - 1) / nwaves;
     const long long begin = wave * per;
     const long long end = min(total, begin + per);
     if (begin >= end) return;
-    // largest t with offsets[t] <= begin
-    int lo = 0, hi = n_tris;
+    // largest v with start(v) <= begin
+    int lo = 0, hi = nv;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (offsets[mid] <= begin) lo = mid; else hi = mid;
+        if (tri_start(base, local_off, mid, nv) <= begin) lo = mid; else hi = mid;
     }
-    int t = lo;
+    int v = lo;
+    long long v_begin = tri_start(base, local_off, v, nv);
+    long long v_end = tri_start(base, local_off, v + 1, nv);
     for (long long item = begin; item < end; ++item) {
-        while (offsets[t + 1] <= item) ++t;
-        const TriSetup s = setup[t];
-        const int local = (int)(item - offsets[t]);
+        while (v_end <= item) {
+            ++v;
+            v_begin = v_end;
+            v_end = tri_start(base, local_off, v + 1, nv);
+        }
+        const int pass = v >= n_tris ? 1 : 0;
+        const int t = v - pass * n_tris;
+        const RasterPass& rp = pass ? P.p[1] : P.p[0];
+        const TriSetup s = setup[v];
+        const int local = (int)(item - v_begin);
         const int tx = s.tx0 + local % s.ntx;
         const int ty = s.ty0 + local / s.ntx;
         const int i = tx * 8 + (lane & 7);
         const int j = ty * 8 + (lane >> 3);
-        if (i >= w || j >= h) continue;
+        if (i >= rp.w || j >= rp.h) continue;
         const int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
         const int64_t X0 = s.x[0], X1 = s.x[1], X2 = s.x[2];
         const int64_t Y0 = s.y[0], Y1 = s.y[1], Y2 = s.y[2];
@@ -203,12 +275,16 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
         if (!(d >= 0.0f && d <= 1.0f)) continue;
         uint32_t bits = __float_as_uint(d);
         if ((bits & 0x7FFFFFFFu) == 0) bits = 0;  // -0 -> +0
-        const size_t k = (size_t)j * (size_t)w + (size_t)i;
-        if (KEY64) {
-            unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
-            atomicMin(reinterpret_cast<unsigned long long*>(out) + k, key);
+        const size_t k = (size_t)j * (size_t)rp.w + (size_t)i;
+        // Stored values only ever decrease, so a plain read that is already
+        // <= the new key proves the atomic would change nothing.
+        if (rp.key64) {
+            unsigned long long* o = reinterpret_cast<unsigned long long*>(rp.out) + k;
+            const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
+            if (*o > key) atomicMin(o, key);
         } else {
-            atomicMin(reinterpret_cast<uint32_t*>(out) + k, bits);
+            uint32_t* o = reinterpret_cast<uint32_t*>(rp.out) + k;
+            if (*o > bits) atomicMin(o, bits);
         }
     }
 }
@@ -219,14 +295,16 @@ __device__ __forceinline__ float lin_depth(float q, float nl, float fl) {
     return num / den;
 }
 
-template <bool SOFT>
+// FS: 0 = HARD6, 1 = SOFT8, 2 = PAPER4
+template <int FS>
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                                                 const float* __restrict__ normals, int n_tris,
                                                 GatherParams P,
                                                 const unsigned long long* __restrict__ gbuf,
                                                 const uint32_t* __restrict__ sm, int w, int h,
                                                 float* __restrict__ feat, uint8_t* __restrict__ mask) {
-    constexpr int C = SOFT ? 8 : 6;
+    constexpr bool SOFT = FS == 1;
+    constexpr int C = FS == 1 ? 8 : (FS == 2 ? 4 : 6);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= w) return;
@@ -302,13 +380,26 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
         const float tq = sn / fmaxf(cl, 1e-3f);
         const float beta = (zf * tau) * (1.0f + 1.5f * fminf(tq, 10.0f));
         mk = (inside && zf > z + beta) ? 1 : 0;
-        f[0] = dv / P.fc;
-        f[1] = n0;
-        f[2] = n1;
-        f[3] = n2;
-        f[4] = (z - zf) / P.fl;
-        f[5] = z / P.fl;
-        if (SOFT) {
+        if constexpr (FS == 2) {
+            // c_e with the emitter-size offset, z/z_f, z - z_f, c_c/d
+            float vv = vx * vx + vy * vy;
+            vv = vv + vz * vz;
+            float cc = n0 * vx + n1 * vy;
+            cc = cc + n2 * vz;
+            cc = cc / sqrtf(vv);
+            f[0] = cl + P.r_e / 0.0625f;
+            f[1] = z / zf;
+            f[2] = (z - zf) / P.fl;
+            f[3] = cc / dv;
+        } else {
+            f[0] = dv / P.fc;
+            f[1] = n0;
+            f[2] = n1;
+            f[3] = n2;
+            f[4] = (z - zf) / P.fl;
+            f[5] = z / P.fl;
+        }
+        if constexpr (SOFT) {
             float zb = zf;
             if (inside) {
                 const float thr = zf - beta;
@@ -343,56 +434,65 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 size_t raster_workspace_bytes(int n_tris) {
-    return align256((size_t)n_tris * sizeof(TriSetup)) + align256((size_t)n_tris * 4) +
-           align256(((size_t)n_tris + 1) * 8);
+    const size_t nv = 2 * (size_t)n_tris, nblk = (nv + 255) / 256;
+    return align256(nv * sizeof(TriSetup)) + align256(nv * 4) + align256(nblk * 4) +
+           align256((nblk + 1) * 8);
 }
 
-hipError_t raster(const float* tris, int n_tris, const Mat4& m, int w, int h, bool key64,
-                  void* out, void* ws, hipStream_t s) {
-    const size_t npix = (size_t)w * (size_t)h;
-    const int fill_blocks = (int)min((size_t)4096, (npix + 255) / 256);
-    const char* sfx = key64 ? " camera" : " light";
+hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws, hipStream_t s) {
+    const char* sfx = P.npass == 2 ? " light+camera" : (P.p[0].key64 ? " camera" : " light");
+    FillJob f[2] = {{nullptr, 0, 0}, {nullptr, 0, 0}};
+    size_t most = 0;
+    for (int k = 0; k < P.npass; ++k) {
+        const RasterPass& rp = P.p[k];
+        f[k].p = rp.out;
+        f[k].bytes = (size_t)rp.w * rp.h * (rp.key64 ? 8 : 4);
+        f[k].pattern = rp.key64 ? kEmptyKey : (((unsigned long long)kEmptyDepth << 32) | kEmptyDepth);
+        most = max(most, f[k].bytes);
+    }
     {
         TraceScope ts("clear", sfx, s);
-        if (key64)
-            k_fill_u64<<<fill_blocks, 256, 0, s>>>(reinterpret_cast<unsigned long long*>(out), npix, kEmptyKey);
-        else
-            k_fill_u32<<<fill_blocks, 256, 0, s>>>(reinterpret_cast<uint32_t*>(out), npix, kEmptyDepth);
+        const int blocks = (int)min((size_t)2048, (most / 16 + 255) / 256 + 1);
+        k_fill2<<<blocks, 256, 0, s>>>(f[0], f[1]);
     }
     if (n_tris == 0) return hipGetLastError();
-    char* base = reinterpret_cast<char*>(ws);
-    TriSetup* setup = reinterpret_cast<TriSetup*>(base);
-    int* counts = reinterpret_cast<int*>(base + align256((size_t)n_tris * sizeof(TriSetup)));
-    long long* offsets =
-        reinterpret_cast<long long*>(reinterpret_cast<char*>(counts) + align256((size_t)n_tris * 4));
+    const int nv = P.npass * n_tris;
+    const int nblk = (nv + 255) / 256;
+    char* wsb = reinterpret_cast<char*>(ws);
+    TriSetup* setup = reinterpret_cast<TriSetup*>(wsb);
+    wsb += align256((size_t)nv * sizeof(TriSetup));
+    int* local_off = reinterpret_cast<int*>(wsb);
+    wsb += align256((size_t)nv * 4);
+    int* block_sum = reinterpret_cast<int*>(wsb);
+    wsb += align256((size_t)nblk * 4);
+    long long* base = reinterpret_cast<long long*>(wsb);
     {
         TraceScope ts("tri_setup", sfx, s);
-        k_tri_setup<<<(n_tris + 255) / 256, 256, 0, s>>>(tris, n_tris, m, w, h, setup, counts);
+        k_tri_setup<<<nblk, 256, 0, s>>>(tris, n_tris, P, setup, local_off, block_sum);
     }
     {
         TraceScope ts("tile_scan", sfx, s);
-        k_scan<<<1, kScanThreads, 0, s>>>(counts, n_tris, offsets);
+        k_block_scan<<<1, kScanThreads, 0, s>>>(block_sum, nblk, base);
     }
     {
         TraceScope ts("raster", sfx, s);
-        if (key64)
-            k_raster<true><<<kRasterBlocks, 256, 0, s>>>(setup, offsets, n_tris, w, h, out);
-        else
-            k_raster<false><<<kRasterBlocks, 256, 0, s>>>(setup, offsets, n_tris, w, h, out);
+        k_raster<<<kRasterBlocks, 256, 0, s>>>(setup, base, local_off, n_tris, P);
     }
     return hipGetLastError();
 }
 
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
-                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, bool soft, float* feat,
+                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s) {
     dim3 grid((w + 255) / 256, h);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
-    TraceScope ts("gather", soft ? " soft8" : " hard6", s);
-    if (soft)
-        k_gather<true><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
+    TraceScope ts("gather", fs == 1 ? " soft8" : (fs == 2 ? " paper4" : " hard6"), s);
+    if (fs == 1)
+        k_gather<1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
+    else if (fs == 2)
+        k_gather<2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
     else
-        k_gather<false><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
+        k_gather<0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
     return hipGetLastError();
 }
 

@@ -35,15 +35,15 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status_strings(lib):
-    assert nsm.nsm_abi_version() == 1
+    assert nsm.nsm_abi_version() == 2
     for s in range(8):
         assert nsm.nsm_status_str(s) != "unknown status"
     assert nsm.nsm_status_str(99) == "unknown status"
 
 
 def test_struct_layouts_match_header():
-    # nsm_net_desc: 6 int32; nsm_frame_params: 16+3+1+3+1 + 16+3+3+3+3+4 scalars of 4 bytes
-    assert ctypes.sizeof(_lib.NetDesc) == 24
+    # nsm_net_desc: 11 int32; nsm_frame_params: 16+3+1+3+1 + 16+3+3+3+3+4 scalars of 4 bytes
+    assert ctypes.sizeof(_lib.NetDesc) == 44
     assert ctypes.sizeof(_lib.FrameParams) == 4 * (16 + 3 + 1 + 3 + 1 + 16 + 3 + 3 + 3 + 3 + 4)
 
 
@@ -91,6 +91,23 @@ def test_create_validation_and_param_counts():
     with pytest.raises(nsm.NsmError) as e:
         nsm.nsm_create(6, (16, 32, 64), 7)
     assert e.value.status == 1
+    # the paper's network: 3x3 + 1x1 per level; parameter counts of the 3- and 5-level plans
+    ctx = nsm.nsm_create(4, (16, 32, 64, 128, 256), "bf16", "paper")
+    assert nsm.nsm_param_count(ctx) == 653648 + 1 + sum(
+        [16, 16, 32, 32, 64, 64, 128, 128, 256, 128, 128, 64, 64, 32, 32, 16, 16, 16])
+    with pytest.raises(nsm.NsmError) as e:                # 5 levels: H, W divisible by 16
+        nsm.nsm_workspace_bytes(ctx, 1, 1032, 2048)
+    assert e.value.status == 2
+    with pytest.raises(nsm.NsmError) as e:                # no backward for this architecture
+        nsm.nsm_workspace_bytes(ctx, 1, 1024, 2048, training=1)
+    assert e.value.status == 3
+    nsm.nsm_destroy(ctx)
+    ctx = nsm.nsm_create(4, (16, 32, 64), "f32", "paper")
+    assert nsm.nsm_param_count(ctx) == 39248 + 1 + sum([16, 16, 32, 32, 64, 32, 32, 16, 16, 16])
+    nsm.nsm_destroy(ctx)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_create(4, (16, 32, 64, 128), "f32", "paper")  # 4 levels: no kernels
+    assert e.value.status == 3
 
 
 def test_features_validation():

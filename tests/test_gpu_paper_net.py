@@ -1,0 +1,98 @@
+"""GPU parity of the paper's own network (3x3 + 1x1 per level, average
+pooling, sum skip, no level-0 skip) and of the PAPER4 features.
+
+FP32: norm-wise 1e-5 on logits and visibility vs the FP64 oracle;
+BF16 / FP16: max |vis - vis_fp64| <= 2e-2.  Includes the 5-level net at the
+1024x2048 size the paper's layer tables use."""
+import numpy as np
+import pytest
+import torch
+
+import nsm_synth as S
+import oracle
+from oracle import paper_net as pn
+
+pytestmark = pytest.mark.gpu
+P3, P5 = (16, 32, 64), (16, 32, 64, 128, 256)
+
+
+def _net(widths, dtype, flat):
+    from paper_2301_05262_amd.api import ShadowNet
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    m = ShadowNet(4, widths, dtype, arch="paper")
+    assert m.n_params == flat.size
+    m.set_weights(torch.from_numpy(flat))
+    return m
+
+
+def _weights(widths, seed):
+    rng = S.SplitMix64(seed)
+    parts = []
+    for _, co, k, ci, _ in pn.conv_list(4, widths):
+        parts.append(rng.normals(co * k * k * ci) * np.sqrt(2.0 / (k * k * ci)))
+        parts.append(rng.uniforms(co, -0.1, 0.1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _run(m, feat):
+    vis, lg = m.forward(torch.from_numpy(np.ascontiguousarray(feat, np.float32)).cuda(), logits=True)
+    torch.cuda.synchronize()
+    return vis.cpu().numpy().astype(np.float64), lg.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("widths,shape", [(P3, (2, 64, 96)), (P3, (1, 36, 52)), (P5, (2, 64, 96)),
+                                          (P5, (1, 48, 80))])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_paper_net_random(widths, shape, dtype):
+    n, h, w = shape
+    flat = _weights(widths, 41)
+    feat = S.SplitMix64(42).uniforms(n * h * w * 4, -1, 1).reshape(n, h, w, 4).astype(np.float32)
+    ref = pn.forward(4, widths, flat, feat)
+    vis, lg = _run(_net(widths, dtype, flat), feat)
+    if dtype == "f32":
+        el = np.abs(lg - ref["logits"]).max() / np.abs(ref["logits"]).max()
+        ev = np.abs(vis - ref["vis"]).max() / np.abs(ref["vis"]).max()
+        print(f"[P{len(widths)} {shape} f32] norm-wise logits {el:.2e} vis {ev:.2e}", flush=True)
+        assert el <= 1e-5 and ev <= 1e-5
+    else:
+        e = np.abs(vis - ref["vis"]).max()
+        print(f"[P{len(widths)} {shape} {dtype}] max |vis - fp64| {e:.2e}", flush=True)
+        assert e <= 2e-2
+
+
+def test_paper4_features_bit_exact():
+    from paper_2301_05262_amd.api import FeatureBuilder
+    sc, frames = S.make_train_window(0, 5, width=160, height=96, sm_size=512)
+    fb = FeatureBuilder(sc)
+    for fr in frames[:2]:
+        ref = oracle.build_features(sc, fr, fs="paper4")
+        out = fb(fr, fs="paper4")
+        torch.cuda.synchronize()
+        got = out["feat"].cpu().numpy()
+        assert got.shape[-1] == 4
+        np.testing.assert_array_equal(got.view(np.uint32), ref["feat"].view(np.uint32))
+        np.testing.assert_array_equal(out["mask"].cpu().numpy(), ref["mask"])
+
+
+def test_paper_net_full_size_on_paper4_features():
+    """The 5-level net at 1024x2048 on PAPER4 features of a synthetic frame."""
+    from paper_2301_05262_amd.api import FeatureBuilder
+    sc = S.make_scene("objects60", 0)
+    fr = S.make_frame(sc, 2048, 1024, 2048, light_pos=(0.4, 3.2, -0.3), eye=(3.2, 1.5, 0.3),
+                      target=(0.0, -1.0, 0.0), light_radius=0.1)
+    ref_f = oracle.build_features(sc, fr, fs="paper4")["feat"]
+    got_f = FeatureBuilder(sc)(fr, fs="paper4")["feat"]
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got_f.cpu().numpy().view(np.uint32), ref_f.view(np.uint32))
+    flat = _weights(P5, 43)
+    ref = pn.forward(4, P5, flat, ref_f[None])
+    for dtype in ("f32", "bf16"):
+        vis, lg = _run(_net(P5, dtype, flat), ref_f[None])
+        if dtype == "f32":
+            el = np.abs(lg - ref["logits"]).max() / np.abs(ref["logits"]).max()
+            print(f"[P5 1024x2048 f32] norm-wise logits {el:.2e}", flush=True)
+            assert el <= 1e-5
+        else:
+            e = np.abs(vis - ref["vis"]).max()
+            print(f"[P5 1024x2048 bf16] max |vis - fp64| {e:.2e}", flush=True)
+            assert e <= 2e-2

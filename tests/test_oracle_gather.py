@@ -181,3 +181,29 @@ def test_soft_channels():
     lit = (o["mask"] == 0) & fg & (np.abs(o["pos"][..., 1] + 1.0) < 1e-5)
     far_lit = lit & (np.hypot(o["pos"][..., 0], o["pos"][..., 2]) > 0.9)
     np.testing.assert_allclose(f[far_lit][:, 7] * fr.light_far, o["aux"][far_lit][:, 1], rtol=1e-6)
+
+
+def test_paper4_channels_on_ground_plane():
+    """The paper's feature set (Sec. 3.2): c_e + size code, z/z_f, z - z_f, c_c/d,
+    checked against the cosines computed directly from the receiver positions."""
+    sc = _scene([ground_quad(half=1.5)])
+    fr = make_frame(sc, 96, 64, 512, light_pos=(0.2, 3.0, 0.1), eye=(2.8, 1.4, 1.1),
+                    target=(0.0, -1.0, 0.0), light_radius=0.125)
+    o = oracle.build_features(sc, fr, fs="paper4")
+    hard = oracle.build_features(sc, fr)
+    fg = o["gbuf"] != oracle.EMPTY_KEY
+    inside = fg & (o["aux"][..., 3] == 1)
+    f, P = o["feat"].astype(np.float64), o["pos"].astype(np.float64)
+    L, E = np.asarray(fr.light_pos, np.float64), np.asarray(fr.cam_pos, np.float64)
+    l = L - P
+    c_e = l[..., 1] / np.linalg.norm(l, axis=-1)                 # n = +y on the ground
+    v = E - P
+    c_c = v[..., 1] / np.linalg.norm(v, axis=-1)
+    d = hard["feat"][..., 0].astype(np.float64) * fr.cam_far       # view depth
+    np.testing.assert_allclose(f[fg][:, 0], c_e[fg] + 2.0, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(f[fg][:, 3], (c_c / d)[fg], rtol=2e-6)
+    z, zf = o["aux"][..., 0].astype(np.float64), o["aux"][..., 1].astype(np.float64)
+    np.testing.assert_allclose(f[inside][:, 1], (z / zf)[inside], rtol=1e-6)
+    # same depth-test channel as the 6-channel set
+    np.testing.assert_array_equal(o["feat"][..., 2], hard["feat"][..., 4])
+    assert (o["mask"] == hard["mask"]).all()
