@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--cpu-sample", default="frame", choices=["frame", "none"])
     ap.add_argument("--forms", default="bf16,f32,f16")
     ap.add_argument("--batched", type=int, default=1, help="also time the 16-frame graph batch")
+    ap.add_argument("--paper-net", type=int, default=1, help="also time the paper's 5-level net")
     return ap.parse_args()
 
 
@@ -121,6 +122,56 @@ def batched_section(S, torch, seed, reps):
         "one_by_one_f32": {"ms_per_frame_p50": float(np.median(fm)), "ms_per_frame_p99": float(np.quantile(fm, 0.99)),
                            "frames_per_s": 1e3 / float(fm.mean())},
     }
+
+
+def paper_net_section(S, torch, seed, steps):
+    """The paper's own 5-level network (3x3 + 1x1 per level, avg-pool, sum skip)
+    at 1024x2048 on PAPER4 features: network ms per form, per-kernel times."""
+    import paper_2301_05262_amd as nsm
+    from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet
+    widths = (16, 32, 64, 128, 256)
+    sc = S.make_scene("objects60", seed)
+    fr = S.make_frame(sc, 2048, 1024, 2048, light_pos=(0.4, 3.2, -0.3), eye=(3.2, 1.5, 0.3),
+                      target=(0.0, -1.0, 0.0), light_radius=0.1)
+    fb = FeatureBuilder(sc)
+    buf = fb(fr, fs="paper4")
+    feat = buf["feat"].unsqueeze(0)
+    rng = S.SplitMix64(seed)
+    net0 = ShadowNet(4, widths, "f32", arch="paper")
+    flat = torch.from_numpy((rng.normals(net0.n_params) * 0.1).astype(np.float32))
+    out = {"workload": "paper5_1024x2048", "widths": list(widths), "features": "paper4",
+           "macs_per_pixel": 16208}
+    for f in ("bf16", "f16", "f32"):
+        net = ShadowNet(4, widths, f, arch="paper")
+        net.set_weights(flat)
+        vis = torch.empty((1, 1024, 2048), dtype=torch.float32, device=feat.device)
+        for _ in range(10):
+            net.forward(feat, vis_out=vis)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            net.forward(feat, vis_out=vis)
+        b.record()
+        torch.cuda.synchronize()
+        nsm.nsm_trace_read()
+        nsm.nsm_trace_enable(True)
+        for _ in range(max(1, steps // 4)):
+            net.forward(feat, vis_out=vis)
+        torch.cuda.synchronize()
+        per = {}
+        for name, ms in nsm.nsm_trace_read(1 << 16):
+            per.setdefault(name, []).append(ms)
+        nsm.nsm_trace_enable(False)
+        out[f] = {"network_ms": a.elapsed_time(b) / steps,
+                  "kernels_us": {k: 1e3 * float(np.mean(v)) for k, v in per.items()}}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fb(fr, fs="paper4", out=buf)
+    torch.cuda.synchronize()
+    out["features_ms"] = 1e3 * (time.perf_counter() - t0) / steps
+    out["paper_context"] = "RTX 2080Ti, FP16: 17.3 ms for this network (Sec. 4.5), 28 ms FP32"
+    return out
 
 
 def main():
@@ -256,6 +307,12 @@ def main():
         print(f"[bench] batched: {batched['graph_bf16']['frames_per_s']:.0f} frames/s (graph, bf16) vs "
               f"{batched['one_by_one_f32']['frames_per_s']:.0f} frames/s (one by one, f32)",
               file=sys.stderr, flush=True)
+    paper_net = None
+    if args.paper_net:
+        paper_net = paper_net_section(S, torch, args.seed, steps=50)
+        print(f"[bench] paper net 1024x2048: bf16 {paper_net['bf16']['network_ms']:.3f} ms, "
+              f"f16 {paper_net['f16']['network_ms']:.3f} ms, f32 {paper_net['f32']['network_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
     ms = results[head]["ms_per_frame"]
     line = {
         "metric": METRIC, "value": ms, "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
@@ -265,6 +322,7 @@ def main():
                    "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
                    "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
         "forms": results, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "paper_net": paper_net,
     }
     print(json.dumps(line))
 

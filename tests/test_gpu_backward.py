@@ -77,6 +77,17 @@ def test_backward_matches_oracle(desc, shape):
 
 
 def test_backward_on_soft_shadow_features():
+    """Rendered soft-shadow features are smooth, so thousands of 2x2 pooling
+    windows hold two values that differ by less than float32 accumulation
+    error (1e-7..1e-6): which one is the maximum, and so where the window's
+    gradient goes, is not fixed at float32.  (A float32 PyTorch CPU forward
+    on this input picks a different maximum than float64 in 37 windows and
+    moves 6% of the dfeat elements.)  What the routing cannot change is
+    compared tightly: dW (a sum over all pixels) per stage, and the sum of
+    dfeat over the image per frame and channel (a routed gradient keeps its
+    value, only its pixel changes).  The rest is checked for validity: most
+    elements must still agree and the norm must be kept.  Element-wise parity
+    of dfeat is the random-feature test above."""
     sc, frames = S.make_train_window(0, 3, width=128, height=96, sm_size=512)
     feat = np.stack([oracle.build_features(sc, fr, soft=True)["feat"] for fr in frames[:2]])
     flat = S.he_weights(S.U3_SOFT, 2, bias_scale=0.1)
@@ -84,9 +95,14 @@ def test_backward_on_soft_shadow_features():
     ref_w, ref_f = onet.backward(8, S.U3_SOFT.widths, flat, feat, dvis)
     dw, df = _gpu_grads(_net(S.U3_SOFT, flat), feat, dvis)
     per = _stage_errors(S.U3_SOFT, dw, ref_w)
-    e_f = np.abs(df - ref_f).max() / np.abs(ref_f).max()
-    print(f"[soft features] dW per-stage rel err {per}  dfeat {e_f:.3e}", flush=True)
-    assert max(per.values()) <= REL and e_f <= REL
+    sums = np.abs(df.sum(axis=(1, 2)) - ref_f.sum(axis=(1, 2))) / np.abs(ref_f).sum(axis=(1, 2))
+    agree = (np.abs(df - ref_f) <= REL * np.abs(ref_f).max()).mean()
+    norm = abs(np.linalg.norm(df) - np.linalg.norm(ref_f)) / np.linalg.norm(ref_f)
+    print(f"[soft features] dW per-stage rel err {per}  dfeat channel sums {sums.max():.2e}  "
+          f"agree {agree:.2%}  norm {norm:.2e}", flush=True)
+    assert max(per.values()) <= REL
+    assert sums.max() <= 1e-4
+    assert agree >= 0.85 and norm <= 1e-2
 
 
 def test_finite_differences_on_crop():
@@ -105,19 +121,21 @@ def test_finite_differences_on_crop():
         v = m.forward(f).double()
         return float((v * d).sum())
 
-    # weights with sizeable gradients; step 1e-2: float32 roundoff of J (~1e-6) gives
-    # ~1e-4 absolute FD noise, and ReLU kinks crossed by the step add ~1% relative
+    # weights with sizeable gradients.  Step 1e-3: at 1e-2 the second-order terms
+    # and ReLU kinks crossed by the step already move float64 central differences of
+    # the exact network 5-10% off its gradient; at 1e-3 float32 roundoff of J
+    # (~1e-5 over 256 pixels) gives ~5e-3 absolute noise in the difference quotient
     order = np.argsort(-np.abs(dw))
     rng = S.SplitMix64(28)
     pick = sorted({int(order[int(rng.uniform(0, 400))]) for _ in range(25)})
     assert abs(dw[pick]).min() > 5e-2
     for i in pick:
-        hstep = 1e-2
+        hstep = 1e-3
         p, q = flat.astype(np.float64).copy(), flat.astype(np.float64).copy()
         p[i] += hstep
         q[i] -= hstep
         fd = (J(p) - J(q)) / (2 * hstep)
-        assert abs(fd - dw[i]) <= 3e-2 * abs(dw[i]) + 1e-3, (i, fd, dw[i])
+        assert abs(fd - dw[i]) <= 3e-2 * abs(dw[i]) + 1e-2, (i, fd, dw[i])
 
 
 def test_autograd_function_and_training_step():
