@@ -30,6 +30,19 @@ METRIC = "ms/frame 1080p shadow-net inference, BF16 vs FP32, at stated visibilit
 HBM_PEAK = 8.0e12                         # B/s
 MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}   # dense FLOP/s
 WORKLOAD = "hard_1080p"
+CALIB_COPY_BYTES = 256 << 20
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "hbm_traffic_1080p_bf16.md")
+
+# traced kernel name (BF16 form) -> kernel symbol as the counter summary names it
+KERNEL_SYMBOL = {
+    "raster light+camera": "k_raster",
+    "gather hard6": "k_gather<0>",
+    "conv3x3 6+0->16 Pool bf16": "k_conv3x3<bf16, true, 6, 0, 16, Pool, 8>",
+    "conv3x3 16+0->32 Pool bf16": "k_conv3x3<bf16, false, 16, 0, 32, Pool, 8>",
+    "conv3x3 32+0->64 Store bf16": "k_conv3x3<bf16, false, 32, 0, 64, Store, 8>",
+    "conv3x3 32+64->32 Store phase bf16": "k_conv3x3_up<bf16, 32, 64, 32, Store, 16, 4>",
+    "conv3x3 16+32->16 Head phase bf16": "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 8>",
+}
 
 
 def parse():
@@ -42,6 +55,9 @@ def parse():
     ap.add_argument("--forms", default="bf16,f32,f16")
     ap.add_argument("--batched", type=int, default=1, help="also time the 16-frame graph batch")
     ap.add_argument("--paper-net", type=int, default=1, help="also time the paper's 5-level net")
+    ap.add_argument("--training", type=int, default=1, help="also time the 32-frame FP32 training step")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="end with one plain 256 MiB device copy (the scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -67,7 +83,25 @@ def stage_costs(widths, c_in, h, w, dtype):
     k = f"conv3x3 {w0}+{w1}->{w0} Head"
     fl, by = out[k]
     out[k] = (fl + 2.0 * L0 * w0, by)          # the fused 1x1 head
+    # decoder stages at these sizes run as one phase-form launch (interior
+    # tiles in the phase form, border bands in the general form)
+    for key in (f"conv3x3 {w1}+{w2}->{w1} Store", f"conv3x3 {w0}+{w1}->{w0} Head"):
+        out[key + " phase"] = out[key]
     return out
+
+
+def _base(name):
+    """Traced kernel name without its trailing storage-type suffix."""
+    head, _, last = name.rpartition(" ")
+    return head if last in ("bf16", "f16", "f32") else name
+
+
+def raster_costs(n_tris, h, w, sm):
+    """Algorithmic HBM bytes of the fused light + camera z-buffer: each target
+    read and written once (u32 shadow map, u64 camera keys) plus one 64-byte
+    setup record per triangle and pass."""
+    tgt = sm * sm * 4 + h * w * 8
+    return {"raster light+camera": (0.0, 2.0 * tgt + 2 * n_tris * 64)}
 
 
 def batched_section(S, torch, seed, reps):
@@ -122,6 +156,52 @@ def batched_section(S, torch, seed, reps):
         "one_by_one_f32": {"ms_per_frame_p50": float(np.median(fm)), "ms_per_frame_p99": float(np.quantile(fm, 0.99)),
                            "frames_per_s": 1e3 / float(fm.mean())},
     }
+
+
+def training_section(S, torch, seed, steps):
+    """One training step of the soft-shadow net (FP32, the differentiation
+    form) on 8 windows x 4 frames of 512x512: SOFT8 features of all 32 frames,
+    forward, MSE loss gradient, backward with recomputed activations (dW and
+    dfeatures).  Targets are fixed synthetic visibilities in [0, 1] (the
+    64-sample ray-cast targets are data generation, not part of a step)."""
+    from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet
+    wins = [S.make_train_window(seed, k) for k in range(8)]
+    builders = [FeatureBuilder(sc) for sc, _ in wins]
+    frames = [(b, fr) for b, (_, frs) in zip(builders, wins) for fr in frs]
+    n = len(frames)
+    feat = torch.empty((n, 512, 512, 8), dtype=torch.float32, device="cuda")
+    bufs = [b(fr, soft=True) for b, fr in frames]
+    rng = S.SplitMix64(seed + 7)
+    target = torch.from_numpy(rng.uniforms(n * 512 * 512, 0.0, 1.0).reshape(n, 512, 512).astype(np.float32)).cuda()
+    net = ShadowNet(8, S.U3_SOFT.widths, "f32")
+    net.set_weights(torch.from_numpy(S.he_weights(S.U3_SOFT, seed)))
+    dw = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+
+    def step():
+        for k, (b, fr) in enumerate(frames):
+            b(fr, soft=True, out=bufs[k])
+            feat[k].copy_(bufs[k]["feat"])
+        vis = net.forward(feat)
+        dvis = (2.0 / vis.numel()) * (vis - target)
+        net.backward(feat, dvis, dw_out=dw)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    w0, w1, w2 = S.U3_SOFT.widths
+    L0, L1, L2 = 512 * 512, 256 * 256, 128 * 128
+    macs = 9 * (L0 * w0 * 8 + L1 * w1 * w0 + L2 * w2 * w1 + L1 * w1 * (w1 + w2) + L0 * w0 * (w0 + w1)) + L0 * w0
+    flop = 2.0 * macs * n * 4        # forward + recomputed forward + two backward GEMMs per conv
+    return {"workload": "soft_train_512", "frames": n, "ms_per_step": ms, "dtype": "f32",
+            "tflops_effective": flop / (ms * 1e-3) / 1e12, "flop_per_step": flop,
+            "ideal_ms_at_fp32_mfma_peak": flop / MFMA_PEAK["f32"] * 1e3}
 
 
 def paper_net_section(S, torch, seed, steps):
@@ -272,14 +352,16 @@ def main():
     # roofline of the dominant kernel of the headline (BF16) form
     head = "bf16" if "bf16" in forms else forms[0]
     costs = stage_costs(desc.widths, desc.c_in, H, W, head)
+    costs.update(raster_costs(scene.n_tris, H, W, fr.sm_size))
     kern = results[head]["kernels"]
     dom = max(kern, key=lambda k: kern[k]["avg_us"])
-    base = dom.rsplit(" ", 1)[0]
+    base = _base(dom)
     roof = None
     for f in forms:
         c = stage_costs(desc.widths, desc.c_in, H, W, f)
+        c.update(raster_costs(scene.n_tris, H, W, fr.sm_size))
         for k, v in results[f]["kernels"].items():
-            b = k.rsplit(" ", 1)[0]
+            b = _base(k)
             if b in c:
                 fl, by = c[b]
                 t = v["avg_us"] * 1e-6
@@ -299,13 +381,20 @@ def main():
         else:
             roof = {"kernel": dom, "bound": "hbm", "achieved": by / t / 1e9, "peak": HBM_PEAK / 1e9,
                     "unit": "GB/s", "frac": (by / t) / HBM_PEAK}
-        roof.update({"traffic": None, "avg_us": kern[dom]["avg_us"], "algorithmic_bytes": by,
+        from paper_2301_05262_amd.profsum import recorded_traffic
+        measured = recorded_traffic(TRAFFIC_MD).get(KERNEL_SYMBOL.get(dom, ""), None) if head == "bf16" else None
+        roof.update({"traffic": measured, "avg_us": kern[dom]["avg_us"], "algorithmic_bytes": by,
                      "algorithmic_flops": fl})
     batched = None
     if args.batched:
         batched = batched_section(S, torch, args.seed, reps=20)
         print(f"[bench] batched: {batched['graph_bf16']['frames_per_s']:.0f} frames/s (graph, bf16) vs "
               f"{batched['one_by_one_f32']['frames_per_s']:.0f} frames/s (one by one, f32)",
+              file=sys.stderr, flush=True)
+    training = None
+    if args.training:
+        training = training_section(S, torch, args.seed, steps=5)
+        print(f"[bench] training step (32 x 512^2, fp32): {training['ms_per_step']:.2f} ms",
               file=sys.stderr, flush=True)
     paper_net = None
     if args.paper_net:
@@ -322,9 +411,16 @@ def main():
                    "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
                    "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
         "forms": results, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
-        "paper_net": paper_net,
+        "paper_net": paper_net, "training": training,
     }
     print(json.dumps(line))
+    sys.stdout.flush()
+    if args.calib_copy:
+        src = torch.ones(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -131,7 +131,7 @@ const char *nsm_status_str(int status);
  *   tris        [n_tris][3][3] float32, world-space vertices.
  *   tri_normals [n_tris][3] float32 unit face normals.
  *   fp          host; light and camera for this frame.
- *   h, w        screen size (1..8192 each).
+ *   h, w        screen size (1..16384 each); sm_size likewise.
  *   fs          feature set (HARD6, SOFT8 or PAPER4).
  *   gbuf_in     [h][w] uint64 camera key buffer to use as the G-buffer, or
  *               NULL to rasterise it from `tris` with fp->m_cam.
@@ -158,7 +158,10 @@ nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n
  * NSM_F16 run the precision form (activations and 3x3 weights stored in
  * that type, MFMA products accumulated in float32; the paper quantises its
  * network to half precision, Sec. 4.5).  Inputs and outputs of every call
- * stay float32. */
+ * stay float32.  Decoder stages fold the bilinear x2 upsampling into their
+ * weights away from the image border (four phase kernels per stage, formed
+ * in float64 and rounded once to the storage type), so the upsampled tensor
+ * is never rounded to the storage type there. */
 nsm_status nsm_create(const nsm_net_desc *desc, nsm_dtype dtype, nsm_ctx **out);
 nsm_status nsm_destroy(nsm_ctx *ctx);
 

@@ -1,7 +1,10 @@
-// Forward dispatch of the fused conv stages (kernels in conv_kernels.h).
+// Forward dispatch of the fused conv stages (kernels in conv_kernels.h and,
+// for decoder stages, the phase form of conv_up.h plus the general kernel on
+// the border bands).
 #include <hip/hip_runtime.h>
 
 #include "conv_kernels.h"
+#include "conv_up.h"
 
 namespace nsm {
 namespace {
@@ -23,16 +26,47 @@ template <Dt D> constexpr const char* dt_suffix() {
     return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : " f16");
 }
 
+// Tile rows of the phase-form kernel: 16, or 8 where float32 tiles of wide
+// stages would leave room for only one block per CU.
+template <Dt D, int CS, int CU>
+constexpr int up_tile_rows() { return (D == Dt::F32 && CS + CU >= 96) ? 8 : 16; }
+
+constexpr size_t align256c(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <Dt D, int CS, int CU, int CO>
+constexpr size_t stage_packed_bytes() {
+    size_t b = align256c(packed_bytes<D, CS, CU, CO>());
+    if constexpr (CU > 0) b += align256c(UpGeo<D, CS, CU, CO>::BYTES);
+    return b;
+}
+
+template <Dt D, bool F32, int CS, int CU, int CO, OutMode MODE, int TH>
+hipError_t launch_stage(const ConvArgs& a, hipStream_t s, const char* name) {
+    if constexpr (CU > 0 && !F32 && (MODE == OutMode::Store || MODE == OutMode::Head)) {
+        constexpr int THU = up_tile_rows<D, CS, CU>();
+        const int gxt = (a.w + kTW - 1) / kTW, gyt = (a.h + THU - 1) / THU;
+        if (gxt >= 3 && gyt >= 3) {
+            TraceScope ts(name, D == Dt::F32 ? " phase f32" : (D == Dt::BF16 ? " phase bf16" : " phase f16"), s);
+            const void* wup = reinterpret_cast<const char*>(a.wpk) + align256c(packed_bytes<D, CS, CU, CO>());
+            const int blocks = border_tiles_per_image(THU, TH, a.h, a.w) * a.n + (gxt - 2) * (gyt - 2) * a.n;
+            k_conv3x3_up<D, CS, CU, CO, MODE, THU, TH><<<blocks, kThreads, 0, s>>>(a, wup);
+            return hipGetLastError();
+        }
+    }
+    dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH - 1) / TH, a.n);
+    TraceScope ts(name, dt_suffix<D>(), s);
+    k_conv3x3<D, F32, CS, CU, CO, MODE, TH><<<grid, kThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 template <Dt D>
 hipError_t launch(const ConvStage& st, OutMode mode, const ConvArgs& a, hipStream_t s, bool* found) {
 #define NSM_CASE(CS_, CU_, CO_, MODE_, F32_, TH_)                                              \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_ && mode == OutMode::MODE_ &&             \
         a.in_f32 == F32_) {                                                                    \
         *found = true;                                                                         \
-        dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH_ - 1) / TH_, a.n);                          \
-        TraceScope ts("conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_, dt_suffix<D>(), s);      \
-        k_conv3x3<D, F32_, CS_, CU_, CO_, OutMode::MODE_, TH_><<<grid, kThreads, 0, s>>>(a);   \
-        return hipGetLastError();                                                              \
+        return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, TH_>(                      \
+            a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_);                              \
     }
     NSM_STAGES(NSM_CASE)
 #undef NSM_CASE
@@ -40,16 +74,24 @@ hipError_t launch(const ConvStage& st, OutMode mode, const ConvArgs& a, hipStrea
     return hipErrorInvalidValue;
 }
 
+template <Dt D, int CS, int CU, int CO>
+void pack_stage(const float* w, void* out, hipStream_t s) {
+    constexpr size_t nb = packed_bytes<D, CS, CU, CO>();
+    constexpr int total = (int)(nb / 16 * DT<D>::EPB);
+    k_pack<D, CS, CU, CO><<<(total + 255) / 256, 256, 0, s>>>(w, out);
+    if constexpr (CU > 0) {
+        using G = UpGeo<D, CS, CU, CO>;
+        constexpr int tu = (int)(G::SKIP_ELEMS + 4 * G::PHASE_ELEMS);
+        k_pack_up<D, CS, CU, CO><<<(tu + 255) / 256, 256, 0, s>>>(w, reinterpret_cast<char*>(out) + align256c(nb));
+    }
+}
+
 template <Dt D>
 bool pack_dispatch(const ConvStage& st, const float* w, void* out, hipStream_t s, size_t* bytes) {
 #define NSM_PCASE(CS_, CU_, CO_, MODE_, F32_, TH_)                                             \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_) {                                        \
-        constexpr size_t nb = packed_bytes<D, CS_, CU_, CO_>();                                \
-        if (bytes) *bytes = nb;                                                                \
-        if (out) {                                                                             \
-            constexpr int total = (int)(nb / 16 * DT<D>::EPB);                                 \
-            k_pack<D, CS_, CU_, CO_><<<(total + 255) / 256, 256, 0, s>>>(w, out);              \
-        }                                                                                      \
+        if (bytes) *bytes = stage_packed_bytes<D, CS_, CU_, CO_>();                            \
+        if (out) pack_stage<D, CS_, CU_, CO_>(w, out, s);                                      \
         return true;                                                                           \
     }
     NSM_STAGES(NSM_PCASE)

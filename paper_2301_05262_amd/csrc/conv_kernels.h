@@ -126,6 +126,36 @@ __device__ __forceinline__ void unpack_block(const u32x4& r, float* v) {
     for (int e = 0; e < EPB; ++e) v[e] = to_f(t[e]);
 }
 
+// Global -> LDS copy of N1 + N2 16-byte items by the whole block: every load
+// of a thread is issued before its first LDS store, so the tile costs about
+// one memory latency instead of one per item.  src(idx) returns the item,
+// dst(idx, v) stores it.
+template <int N1, int N2, class S1, class D1, class S2, class D2>
+__device__ __forceinline__ void copy_batched(S1 src1, D1 dst1, S2 src2, D2 dst2) {
+    constexpr int P1 = (N1 + kThreads - 1) / kThreads, P2 = (N2 + kThreads - 1) / kThreads;
+    u32x4 v1[P1 > 0 ? P1 : 1], v2[P2 > 0 ? P2 : 1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        const int idx = threadIdx.x + k * kThreads;
+        if (idx < N1) v1[k] = src1(idx);
+    }
+#pragma unroll
+    for (int k = 0; k < P2; ++k) {
+        const int idx = threadIdx.x + k * kThreads;
+        if (idx < N2) v2[k] = src2(idx);
+    }
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        const int idx = threadIdx.x + k * kThreads;
+        if (idx < N1) dst1(idx, v1[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < P2; ++k) {
+        const int idx = threadIdx.x + k * kThreads;
+        if (idx < N2) dst2(idx, v2[k]);
+    }
+}
+
 // Low-res source tile of the upsampled channels: rows/cols y0/2-1 .. y0/2+TH/2
 // (x likewise), each clamped to the low-res image, LCST elements per pixel.
 template <Dt D, int CU, int TH>
@@ -159,9 +189,8 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
     constexpr int NCH_S = CSP / EPB, NCH_U = CU / EPB;
     // phase 1: same-resolution channels, and the low-res source rows
-    if constexpr (NCH_S > 0)
-    for (int idx = threadIdx.x; idx < NPIX * NCH_S; idx += kThreads) {
-        const int pix = idx / NCH_S, ch = idx - pix * NCH_S;
+    auto skip_src = [&](int idx) -> u32x4 {
+        const int pix = idx / (NCH_S > 0 ? NCH_S : 1), ch = idx - pix * NCH_S;
         const int ty = pix / WP, tx = pix - ty * WP;
         const int y = y0 + ty - 1, x = x0 + tx - 1;
         u32x4 v = {0u, 0u, 0u, 0u};
@@ -180,19 +209,28 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
                 v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(in) + p * CS + ch * EPB);
             }
         }
+        return v;
+    };
+    auto skip_dst = [&](int idx, const u32x4& v) {
+        const int pix = idx / (NCH_S > 0 ? NCH_S : 1), ch = idx - pix * NCH_S;
         *reinterpret_cast<u32x4*>(&tile[pix * CST + ch * EPB]) = v;
-    }
+    };
+    constexpr int NLOW = CU > 0 ? LT::LH * LT::LW * NCH_U : 0;
+    const int hl = h >> 1, wl = w >> 1;
+    const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
+    const T* lo = reinterpret_cast<const T*>(low) + (size_t)n * hl * wl * CU;
+    auto low_src = [&](int idx) -> u32x4 {
+        const int pix = idx / (NCH_U > 0 ? NCH_U : 1), ch = idx - pix * NCH_U;
+        const int r = pix / LT::LW, c = pix - r * LT::LW;
+        const int gy = min(max(ly0 + r, 0), hl - 1), gx = min(max(lx0 + c, 0), wl - 1);
+        return *reinterpret_cast<const u32x4*>(lo + ((size_t)gy * wl + gx) * CU + ch * EPB);
+    };
+    auto low_dst = [&](int idx, const u32x4& v) {
+        const int pix = idx / (NCH_U > 0 ? NCH_U : 1), ch = idx - pix * NCH_U;
+        *reinterpret_cast<u32x4*>(&lowt[pix * LT::LCST + ch * EPB]) = v;
+    };
+    copy_batched<NPIX * NCH_S, NLOW>(skip_src, skip_dst, low_src, low_dst);
     if constexpr (CU > 0) {
-        const int hl = h >> 1, wl = w >> 1;
-        const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
-        const T* lo = reinterpret_cast<const T*>(low) + (size_t)n * hl * wl * CU;
-        for (int idx = threadIdx.x; idx < LT::LH * LT::LW * NCH_U; idx += kThreads) {
-            const int pix = idx / NCH_U, ch = idx - pix * NCH_U;
-            const int r = pix / LT::LW, c = pix - r * LT::LW;
-            const int gy = min(max(ly0 + r, 0), hl - 1), gx = min(max(lx0 + c, 0), wl - 1);
-            *reinterpret_cast<u32x4*>(&lowt[pix * LT::LCST + ch * EPB]) =
-                *reinterpret_cast<const u32x4*>(lo + ((size_t)gy * wl + gx) * CU + ch * EPB);
-        }
         __syncthreads();
         // phase 2: upsampled channels from the staged rows
         for (int idx = threadIdx.x; idx < NPIX * NCH_U; idx += kThreads) {
@@ -236,6 +274,36 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
     return xcd * q + min(xcd, r) + k;
 }
 
+// Border tiles of a phase-form decoder launch (conv_up.h): the phase kernel
+// covers the tiles of a band x 32 tiling that are at least one tile away from
+// every edge; this maps a linear index over the rest, in tiles of TH x 32
+// (band is a multiple of TH), to (x0, y0, n): the top band, the bottom band,
+// then the first and last tile columns in between.
+__host__ __device__ __forceinline__ int border_tiles_per_image(int band, int th, int h, int w) {
+    const int gx = (w + kTW - 1) / kTW, gyb = (h + band - 1) / band, ylast = (gyb - 1) * band;
+    return (band / th) * gx + ((h - ylast + th - 1) / th) * gx + ((ylast - band) / th) * 2;
+}
+
+__device__ __forceinline__ void border_tile(int lt, int band, int th, int h, int w, int* x0, int* y0, int* n) {
+    const int gx = (w + kTW - 1) / kTW, gyb = (h + band - 1) / band, ylast = (gyb - 1) * band;
+    const int top = (band / th) * gx, bot = ((h - ylast + th - 1) / th) * gx;
+    const int per = border_tiles_per_image(band, th, h, w);
+    *n = lt / per;
+    int r = lt - *n * per;
+    if (r < top) {
+        *y0 = (r / gx) * th;
+        *x0 = (r % gx) * kTW;
+    } else if (r - top < bot) {
+        r -= top;
+        *y0 = ylast + (r / gx) * th;
+        *x0 = (r % gx) * kTW;
+    } else {
+        r -= top + bot;
+        *y0 = band + (r >> 1) * th;
+        *x0 = (r & 1) ? (gx - 1) * kTW : 0;
+    }
+}
+
 // Store four consecutive channels co..co+3 (fewer at the end of an odd-sized
 // channel vector) of one pixel.
 template <typename T, int CO>
@@ -258,23 +326,27 @@ __device__ __forceinline__ void store4(T* dst, int co, const float* v) {
     }
 }
 
+// LDS elements of one tile of the general kernel (halo tile, then low rows).
+template <Dt D, int CS, int CU, int CO, int TH>
+struct GenTile {
+    static constexpr int TILE = (TH + 2) * (kTW + 2) * Geo<D, CS, CU, CO>::CST;
+    static constexpr int LOW = LowTile<D, CU, TH>::SIZE;
+    static constexpr int LOW_OFF = (TILE + 7) / 8 * 8;   // 16-byte aligned for every storage type
+    static constexpr int ELEMS = LOW_OFF + LOW;
+};
+
+// One TH x 32 output tile at (x0, y0) of image n: the whole stage for it.
 template <Dt D, bool IN_F32, int CS, int CU, int CO, OutMode MODE, int TH>
-__global__ void __launch_bounds__(kThreads) k_conv3x3(ConvArgs a) {
+__device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int n,
+                                          typename DT<D>::T* tile, typename DT<D>::T* lowt) {
     using T = typename DT<D>::T;
     using G = Geo<D, CS, CU, CO>;
     constexpr int EPB = G::EPB, CST = G::CST, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
-    constexpr int HP = TH + 2, WP = kTW + 2, NPIX = HP * WP;
+    constexpr int WP = kTW + 2;
     constexpr int RPW = TH / 4;                 // rows per wave
     constexpr int MF = RPW * 2;                 // M-fragments per wave
     static_assert(MODE != OutMode::Pool || RPW == 2, "pooling needs row pairs per wave");
-
-    __shared__ __attribute__((aligned(16))) T tile[NPIX * CST];
-    __shared__ __attribute__((aligned(16))) T lowt[LowTile<D, CU, TH>::SIZE];
-
     const int h = a.h, w = a.w;
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
-    const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
 
     // ---------------- prologue: halo tile to LDS
     load_halo_tile<D, IN_F32, CS, CU, CST, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
@@ -401,6 +473,17 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3(ConvArgs a) {
             }
         }
     }
+}
+
+template <Dt D, bool IN_F32, int CS, int CU, int CO, OutMode MODE, int TH>
+__global__ void __launch_bounds__(kThreads) k_conv3x3(ConvArgs a) {
+    using T = typename DT<D>::T;
+    using GT = GenTile<D, CS, CU, CO, TH>;
+    __shared__ __attribute__((aligned(16))) T smem[GT::ELEMS];
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    conv_tile<D, IN_F32, CS, CU, CO, MODE, TH>(a, (lt % gx) * kTW, ((lt / gx) % gy) * TH, lt / (gx * gy), smem,
+                                               smem + GT::LOW_OFF);
 }
 
 // Weight repack: OHWI float32 [CO][3][3][CS+CU] -> [NF][NKG][64 lanes][EPB]

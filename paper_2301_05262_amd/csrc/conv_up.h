@@ -1,0 +1,333 @@
+// Decoder stages with the bilinear x2 upsampling folded into the weights.
+//
+// A decoder stage (paper Sec. 4.5) convolves the concatenation [skip, up(low)]
+// with a 3x3 kernel, where up() is bilinear x2 with half-pixel centres: row y
+// of the upsampled image is 1/4 of low row (y-1)/2 and 3/4 of the next one
+// for even y (the reverse for odd y), clamped to the low image.  Both maps are
+// linear, so away from the image border the part of the stage that reads
+// up(low) is itself a 3x3 convolution over the *low-resolution* tile, with a
+// different kernel for each of the four output phases (y mod 2, x mod 2):
+//
+//   out(2i+py, 2j+px) = sum_{ty,tx} Wp[py][px][ty][tx] . low(i-1+ty, j-1+tx)
+//   Wp[py][px][ty][tx] = sum_{ky,kx} C[py][ky][ty] C[px][kx][tx] W[ky][kx]
+//
+// with the 3x3 coupling tables C below (C[p][k][t] = the weight of low tap
+// i-1+t in the upsampled row 2i+p+k-1).  Low taps that fall outside the low
+// image are clamped when the low tile is staged, which is exactly what the
+// clamped interpolation does.  What the phase form cannot express is the
+// conv's zero padding of up() at rows -1 and H and columns -1 and W, so only
+// tiles that stay clear of the first and last row and column use it; the
+// border bands run the general kernel (conv_kernels.h).
+//
+// Gains on MI355X: no interpolation arithmetic at all (it was most of the
+// vector ALU work of the general kernel), a low-resolution tile 4x smaller
+// than the upsampled one, and every low-resolution operand read from LDS
+// feeds the MFMAs of both x-phases.  The MFMA work per output pixel is
+// unchanged (K = 9 * (CS + CU)).
+//
+// Tile: TH rows x 32 columns, 256 threads.  Wave w takes the rows of parity
+// w & 1 in half w >> 1 of the tile, TH/4 rows; each row is two 16-pixel MFMA
+// fragments, the even and the odd columns, so a fragment has one x-phase.
+// The skip tile is stored split by column parity, so that the 16 pixels of a
+// fragment (stride 2 in the image) are consecutive in LDS.
+#pragma once
+#include "conv_kernels.h"
+
+namespace nsm {
+namespace ck {
+
+// C[p][k][t]: weight of low-resolution tap (i - 1 + t) in upsampled row
+// 2i + p + k - 1 (rows of the 3x3 conv window k = 0, 1, 2).
+__host__ __device__ constexpr double up_coupling(int p, int k, int t) {
+    // upsampled row u = 2i + p + k - 1 = 2i + d, d in [-1, 2]
+    // even u = 2m: 1/4 low(m-1) + 3/4 low(m); odd u = 2m+1: 3/4 low(m) + 1/4 low(m+1)
+    const int d = p + k - 1;
+    // d = -1: u = 2(i-1)+1 -> 3/4 low(i-1) + 1/4 low(i)
+    // d =  0: u = 2i       -> 1/4 low(i-1) + 3/4 low(i)
+    // d =  1: u = 2i+1     -> 3/4 low(i)   + 1/4 low(i+1)
+    // d =  2: u = 2(i+1)   -> 1/4 low(i)   + 3/4 low(i+1)
+    return d == -1 ? (t == 0 ? 0.75 : (t == 1 ? 0.25 : 0.0))
+         : d == 0  ? (t == 0 ? 0.25 : (t == 1 ? 0.75 : 0.0))
+         : d == 1  ? (t == 1 ? 0.75 : (t == 2 ? 0.25 : 0.0))
+                   : (t == 1 ? 0.25 : (t == 2 ? 0.75 : 0.0));
+}
+
+template <Dt D, int CS, int CU, int CO>
+struct UpGeo {
+    static constexpr int EPB = DT<D>::EPB;
+    static_assert(CS % EPB == 0 && CU % EPB == 0, "channels must fill whole 16-byte blocks");
+    static constexpr int BPT_S = CS / EPB, BPT_U = CU / EPB;
+    static constexpr int NB_S = 9 * BPT_S, NB_U = 9 * BPT_U;
+    static constexpr int NKG_S = (NB_S + 3) / 4, NKG_U = (NB_U + 3) / 4;
+    static constexpr int NF = (CO + 15) / 16;
+    static constexpr int CSTS = lds_stride<D>(CS), CSTU = lds_stride<D>(CU);
+    // packed weight elements: skip part, then 4 phases of the low-res part
+    static constexpr size_t SKIP_ELEMS = (size_t)NF * NKG_S * 64 * EPB;
+    static constexpr size_t PHASE_ELEMS = (size_t)NF * NKG_U * 64 * EPB;
+    static constexpr size_t BYTES = (SKIP_ELEMS + 4 * PHASE_ELEMS) * sizeof(typename DT<D>::T);
+};
+
+// Tile geometry of the phase kernel.
+template <Dt D, int CS, int CU, int TH>
+struct UpTile {
+    static constexpr int SR = TH + 2, SC = 17;          // skip tile: rows x (2 parity planes x 17)
+    static constexpr int LR = TH / 2 + 2, LC = kTW / 2 + 2;
+    static constexpr int SKIP = SR * 2 * SC * lds_stride<D>(CS);
+    static constexpr int LOW = LR * LC * lds_stride<D>(CU);
+};
+
+// Pack the phase-form weights from OHWI float32 W[CO][3][3][CS+CU]:
+// [NF][NKG_S][64][EPB] for the skip channels (k-block b = (tap, channel
+// block) with tap = ky * 3 + kx), then for each phase py * 2 + px
+// [NF][NKG_U][64][EPB] with k-block b = (low tap ty * 3 + tx, channel block).
+// The phase kernels are formed in float64 and rounded once.
+template <Dt D, int CS, int CU, int CO>
+__global__ void k_pack_up(const float* __restrict__ w, void* __restrict__ out) {
+    using T = typename DT<D>::T;
+    using G = UpGeo<D, CS, CU, CO>;
+    constexpr int EPB = G::EPB, CIN = CS + CU;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = G::SKIP_ELEMS + 4 * G::PHASE_ELEMS;
+    if (idx >= total) return;
+    const int e = (int)(idx % EPB);
+    const int lane = (int)((idx / EPB) % 64);
+    const int co_l = lane & 15, g = lane >> 4;
+    double v = 0.0;
+    if (idx < G::SKIP_ELEMS) {
+        const int q = (int)((idx / (EPB * 64)) % G::NKG_S);
+        const int f = (int)(idx / ((size_t)EPB * 64 * G::NKG_S));
+        const int co = f * 16 + co_l, b = 4 * q + g;
+        if (b < G::NB_S && co < CO) {
+            const int tap = b / G::BPT_S, cb = b % G::BPT_S;
+            v = w[((size_t)co * 9 + tap) * CIN + cb * EPB + e];
+        }
+    } else {
+        const size_t r = idx - G::SKIP_ELEMS;
+        const int q = (int)((r / (EPB * 64)) % G::NKG_U);
+        const int f = (int)((r / ((size_t)EPB * 64 * G::NKG_U)) % G::NF);
+        const int ph = (int)(r / G::PHASE_ELEMS);
+        const int py = ph >> 1, px = ph & 1;
+        const int co = f * 16 + co_l, b = 4 * q + g;
+        if (b < G::NB_U && co < CO) {
+            const int t = b / G::BPT_U, cb = b % G::BPT_U;
+            const int ty = t / 3, tx = t % 3;
+            const int ch = CS + cb * EPB + e;
+            for (int ky = 0; ky < 3; ++ky)
+                for (int kx = 0; kx < 3; ++kx) {
+                    const double c = up_coupling(py, ky, ty) * up_coupling(px, kx, tx);
+                    if (c != 0.0) v += c * (double)w[((size_t)co * 9 + ky * 3 + kx) * CIN + ch];
+                }
+        }
+    }
+    reinterpret_cast<T*>(out)[idx] = from_f<T>((float)v);
+}
+
+// One launch covers the whole stage: blocks [0, nb) take the border tiles
+// (the general kernel's TH_G x 32 tiles in the top and bottom bands and the
+// first and last tile columns, border_tile()), the remaining blocks the
+// interior TH x 32 tiles, none of whose pixels lies in the first or last row
+// or column.  Border blocks come first so that their slower general path
+// overlaps the phase-form blocks.  MODE is Store or Head.
+template <Dt D, int CS, int CU, int CO, OutMode MODE, int TH, int TH_G>
+__global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void* __restrict__ wup) {
+    using T = typename DT<D>::T;
+    using G = UpGeo<D, CS, CU, CO>;
+    using UT = UpTile<D, CS, CU, TH>;
+    using GT = GenTile<D, CS, CU, CO, TH_G>;
+    constexpr int EPB = G::EPB, NF = G::NF, CSTS = G::CSTS, CSTU = G::CSTU;
+    constexpr int RW = TH / 4;                  // rows per wave
+    static_assert(TH % 8 == 0 && TH % TH_G == 0, "each wave needs rows of one parity in one half of the tile");
+    static_assert(MODE == OutMode::Store || MODE == OutMode::Head, "decoder stages store or end in the head");
+    constexpr int LOW_OFF = (UT::SKIP + 7) / 8 * 8;
+    constexpr int ELEMS = (LOW_OFF + UT::LOW) > GT::ELEMS ? (LOW_OFF + UT::LOW) : GT::ELEMS;
+
+    __shared__ __attribute__((aligned(16))) T smem[ELEMS];
+
+    const int h = a.h, w = a.w, hl = h >> 1, wl = w >> 1;
+    const int nb = border_tiles_per_image(TH, TH_G, h, w) * a.n;
+    if ((int)blockIdx.x < nb) {
+        int bx, by, bn;
+        border_tile(blockIdx.x, TH, TH_G, h, w, &bx, &by, &bn);
+        conv_tile<D, false, CS, CU, CO, MODE, TH_G>(a, bx, by, bn, smem, smem + GT::LOW_OFF);
+        return;
+    }
+    T* skip = smem;
+    T* lowt = smem + LOW_OFF;
+    const int gx = (w + kTW - 1) / kTW - 2, gy = (h + TH - 1) / TH - 2;
+    const int lt = xcd_remap(blockIdx.x - nb, gx * gy * a.n);
+    const int x0 = (lt % gx + 1) * kTW, y0 = ((lt / gx) % gy + 1) * TH, n = lt / (gx * gy);
+
+    // ---------------- prologue: skip tile (split by column parity) and low tile
+    {
+        const T* in = reinterpret_cast<const T*>(a.in);
+        const T* lo = reinterpret_cast<const T*>(a.low) + (size_t)n * hl * wl * CU;
+        const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
+        auto skip_src = [&](int idx) -> u32x4 {
+            const int cb = idx % G::BPT_S, pix = idx / G::BPT_S;
+            const int r = pix / 34, c = pix - r * 34;
+            const int y = y0 + r - 1, x = x0 + c - 1;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (y >= 0 && y < h && x >= 0 && x < w)
+                v = *reinterpret_cast<const u32x4*>(in + (((size_t)n * h + y) * w + x) * CS + cb * EPB);
+            return v;
+        };
+        auto skip_dst = [&](int idx, const u32x4& v) {
+            const int cb = idx % G::BPT_S, pix = idx / G::BPT_S;
+            const int r = pix / 34, c = pix - r * 34;
+            *reinterpret_cast<u32x4*>(&skip[((r * 2 + (c & 1)) * UT::SC + (c >> 1)) * CSTS + cb * EPB]) = v;
+        };
+        auto low_src = [&](int idx) -> u32x4 {
+            const int cb = idx % G::BPT_U, pix = idx / G::BPT_U;
+            const int r = pix / UT::LC, c = pix - r * UT::LC;
+            const int gyl = min(max(ly0 + r, 0), hl - 1), gxl = min(max(lx0 + c, 0), wl - 1);
+            return *reinterpret_cast<const u32x4*>(lo + ((size_t)gyl * wl + gxl) * CU + cb * EPB);
+        };
+        auto low_dst = [&](int idx, const u32x4& v) {
+            const int cb = idx % G::BPT_U, pix = idx / G::BPT_U;
+            *reinterpret_cast<u32x4*>(&lowt[pix * CSTU + cb * EPB]) = v;
+        };
+        copy_batched<UT::SR * 34 * G::BPT_S, UT::LR * UT::LC * G::BPT_U>(skip_src, skip_dst, low_src, low_dst);
+    }
+    __syncthreads();
+
+    // ---------------- main loop
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = lane & 15, g = lane >> 4;
+    const int py = wave & 1, half = wave >> 1;
+    f32x4 acc[RW][2][NF];
+#pragma unroll
+    for (int m = 0; m < RW; ++m)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[m][p][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // skip channels: ordinary 3x3 taps over the full-resolution tile
+    const u32x4* wsk = reinterpret_cast<const u32x4*>(wup);
+#pragma unroll
+    for (int q = 0; q < G::NKG_S; ++q) {
+        u32x4 wf[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) wf[f] = wsk[(f * G::NKG_S + q) * 64 + lane];
+        int b = 4 * q + g;
+        if (b >= G::NB_S) b = G::NB_S - 1;     // padding k: weights are zero there
+        const int tap = b / G::BPT_S, cb = b - tap * G::BPT_S;
+        const int ky = tap / 3, kx = tap - ky * 3;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int row = py + 2 * (RW * half + m) + ky;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int c = p + kx;
+                const u32x4 xb = *reinterpret_cast<const u32x4*>(
+                    &skip[((row * 2 + (c & 1)) * UT::SC + j + (c >> 1)) * CSTS + cb * EPB]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) acc[m][p][f] = mfma_kgroup<D>(wf[f], xb, acc[m][p][f]);
+            }
+        }
+    }
+    // upsampled channels: phase kernels over the low-resolution tile
+    const u32x4* wlo = wsk + (size_t)NF * G::NKG_S * 64;
+#pragma unroll
+    for (int q = 0; q < G::NKG_U; ++q) {
+        u32x4 w0[NF], w1[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            w0[f] = wlo[(((py * 2 + 0) * NF + f) * G::NKG_U + q) * 64 + lane];
+            w1[f] = wlo[(((py * 2 + 1) * NF + f) * G::NKG_U + q) * 64 + lane];
+        }
+        int b = 4 * q + g;
+        if (b >= G::NB_U) b = G::NB_U - 1;
+        const int t = b / G::BPT_U, cb = b - t * G::BPT_U;
+        const int ty = t / 3, tx = t - ty * 3;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int r = RW * half + m + ty;
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&lowt[(r * UT::LC + j + tx) * CSTU + cb * EPB]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                acc[m][0][f] = mfma_kgroup<D>(w0[f], xb, acc[m][0][f]);
+                acc[m][1][f] = mfma_kgroup<D>(w1[f], xb, acc[m][1][f]);
+            }
+        }
+    }
+
+    // ---------------- epilogue: bias + ReLU, then store or the 1x1 head
+    float bias[NF][4];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int co = f * 16 + 4 * g + e;
+            bias[f][e] = (co < CO) ? a.bias[co] : 0.0f;
+        }
+#pragma unroll
+    for (int m = 0; m < RW; ++m)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[m][p][f][e] = fmaxf(acc[m][p][f][e] + bias[f][e], 0.0f);
+
+    if constexpr (MODE == OutMode::Head) {
+        float hw[NF][4];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = f * 16 + 4 * g + e;
+                hw[f][e] = (co < CO) ? a.head_w[co] : 0.0f;
+            }
+        const float hb = a.head_w[CO];
+#pragma unroll
+        for (int m = 0; m < RW; ++m)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int y = y0 + py + 2 * (RW * half + m), x = x0 + 2 * j + p;
+                const bool ok = y < h && x < w;
+                const size_t pi = ((size_t)n * h + y) * w + x;
+                float s = 0.0f;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) s += hw[f][e] * acc[m][p][f][e];
+                s += __shfl_xor(s, 16);
+                s += __shfl_xor(s, 32);
+                if (ok && g == 0) {
+                    const float logit = s + hb;
+                    a.vis[pi] = 1.0f / (1.0f + __expf(-logit));
+                    if (a.logits) a.logits[pi] = logit;
+                }
+                if (ok && a.act_out) {
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const int co = f * 16 + 4 * g;
+                        if (co < CO) *reinterpret_cast<f32x4*>(a.act_out + pi * CO + co) = acc[m][p][f];
+                    }
+                }
+            }
+    } else {
+        T* out = reinterpret_cast<T*>(a.out);
+#pragma unroll
+        for (int m = 0; m < RW; ++m)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int y = y0 + py + 2 * (RW * half + m), x = x0 + 2 * j + p;
+                if (y < h && x < w) {
+                    const size_t pi = ((size_t)n * h + y) * w + x;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const int co = f * 16 + 4 * g;
+                        if (co < CO) {
+                            float v4[4] = {acc[m][p][f][0], acc[m][p][f][1], acc[m][p][f][2], acc[m][p][f][3]};
+                            store4<T, CO>(out + pi * CO + co, co, v4);
+                        }
+                    }
+                }
+            }
+    }
+}
+
+}  // namespace ck
+}  // namespace nsm

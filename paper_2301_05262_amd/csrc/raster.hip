@@ -15,9 +15,8 @@
 //
 // Work distribution (MI355X): one thread per triangle sets up its snapped
 // vertices and the 8x8-texel tiles its bounding box touches; a one-block scan
-// turns tile counts into offsets; then every 64-lane wave rasterises one
-// (triangle, tile) item at a time, one lane per texel, walking a contiguous
-// run of items so that consecutive items mostly share a triangle.
+// turns tile counts into offsets; then every 64-lane wave rasterises chunks
+// of 64 consecutive (triangle, tile) items, one lane per texel.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -30,7 +29,7 @@ namespace {
 constexpr uint32_t kEmptyDepth = 0x7F800000u;
 constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr int kScanThreads = 1024;
-constexpr int kRasterBlocks = 4096;   // 16384 waves: ~64 per CU on 256 CUs
+constexpr int kRasterBlocks = 2048;   // 8192 waves: 32 per CU on 256 CUs, one resident round
 
 __device__ __forceinline__ void to_clip(const Mat4& M, float x, float y, float z, float c[4]) {
 #pragma unroll
@@ -54,9 +53,7 @@ struct FillJob {
     unsigned long long pattern;   // 8-byte pattern repeated
 };
 
-__global__ void __launch_bounds__(256) k_fill2(FillJob a, FillJob b) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fill2(FillJob a, FillJob b, size_t tid, size_t stride) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const FillJob f = j ? b : a;
@@ -74,10 +71,29 @@ __global__ void __launch_bounds__(256) k_fill2(FillJob a, FillJob b) {
     }
 }
 
+// Per-triangle float64 coefficients of the coverage and depth arithmetic,
+// read with scalar loads by the raster loop.  Edge k (opposite vertex k, from
+// vertex a to vertex b) is E_k(px, py) = dx_k py - dy_k px + c_k with
+// dx_k = Xb - Xa, dy_k = Yb - Ya, c_k = dy_k Xa - dx_k Ya: all exact integers.
+struct alignas(16) TriCoef {
+    double dx[3], dy[3], c[3];
+    double z[3];          // vertex ndc depths (float32 values)
+    double area;          // doubled area (> 0)
+    double inv_area;      // 1 / area rounded to nearest
+    int32_t incl;         // bit k: edge k owns the pixels exactly on it
+    int32_t pad[3];
+};
+static_assert(sizeof(TriCoef) == 128, "TriCoef must stay 128 bytes");
+
+__device__ __forceinline__ bool edge_owns(int64_t dx, int64_t dy) {
+    return dy > 0 || (dy == 0 && dx < 0);
+}
+
 // Snap one triangle, order it counter-clockwise and count the 8x8 tiles of
 // its texel bounding box (0 if dropped, degenerate or off-screen).
 __device__ __forceinline__ int tri_setup_one(const float* __restrict__ tris, int t, const Mat4& M,
-                                             int w, int h, TriSetup* __restrict__ setup) {
+                                             int w, int h, TriSetup* __restrict__ setup,
+                                             TriCoef* __restrict__ coef) {
     const float* T = tris + 9 * (size_t)t;
     const float fw = (float)w, fh = (float)h;
     int64_t X[3], Y[3];
@@ -141,6 +157,21 @@ __device__ __forceinline__ int tri_setup_one(const float* __restrict__ tris, int
         for (int v = 0; v < 3; ++v) { s.x[v] = 0; s.y[v] = 0; s.z[v] = 0.0f; }
     }
     setup[t] = s;
+    TriCoef c;
+    c.incl = 0;
+    c.pad[0] = c.pad[1] = c.pad[2] = 0;
+    for (int k = 0; k < 3; ++k) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        const int64_t dx = (int64_t)s.x[b] - s.x[a], dy = (int64_t)s.y[b] - s.y[a];
+        c.dx[k] = (double)dx;
+        c.dy[k] = (double)dy;
+        c.c[k] = fma((double)dy, (double)s.x[a], -((double)dx * (double)s.y[a]));
+        c.z[k] = (double)s.z[k];
+        if (edge_owns(dx, dy)) c.incl |= 1 << k;
+    }
+    c.area = (double)s.area;
+    c.inv_area = count ? 1.0 / c.area : 0.0;
+    coef[t] = c;
     return count;
 }
 
@@ -162,16 +193,26 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
     return off + incl - v;
 }
 
+// Blocks [0, nblk) set up one virtual triangle per thread (v = pass * n_tris
+// + t) and scan their tile counts; the remaining blocks clear the targets.
+// The raster kernel that follows on the stream sees both finished.
 __global__ void __launch_bounds__(256) k_tri_setup(const float* __restrict__ tris, int n_tris,
                                                    RasterPasses P, TriSetup* __restrict__ setup,
-                                                   int* __restrict__ local_off, int* __restrict__ block_sum) {
-    // virtual triangle v = pass * n_tris + t
+                                                   TriCoef* __restrict__ coef,
+                                                   int* __restrict__ local_off, int* __restrict__ block_sum,
+                                                   int nblk, FillJob fa, FillJob fb) {
+    if ((int)blockIdx.x >= nblk) {
+        const size_t fill_threads = (size_t)(gridDim.x - nblk) * blockDim.x;
+        fill2(fa, fb, (size_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, fill_threads);
+        return;
+    }
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     int count = 0;
     if (v < P.npass * n_tris) {
         const int pass = v >= n_tris ? 1 : 0;
         const RasterPass& rp = pass ? P.p[1] : P.p[0];
-        count = tri_setup_one(tris, v - pass * n_tris, rp.m, rp.w, rp.h, setup + pass * n_tris);
+        count = tri_setup_one(tris, v - pass * n_tris, rp.m, rp.w, rp.h, setup + pass * n_tris,
+                              coef + pass * n_tris);
     }
     int total;
     const int off = block_exclusive_scan(count, &total);
@@ -215,76 +256,106 @@ __device__ __forceinline__ long long tri_start(const long long* __restrict__ bas
     return (t >= n) ? base[(n + 255) >> 8] : base[t >> 8] + local_off[t];
 }
 
-__device__ __forceinline__ bool edge_inclusive(int64_t dx, int64_t dy) {
-    return dy > 0 || (dy == 0 && dx < 0);
+
+// The virtual triangle holding tile item `item` (the largest v with
+// start(v) <= item) and the item's index within that triangle.  Two short
+// binary searches: over the block bases, then over the block's local offsets.
+__device__ __forceinline__ int find_tri(const long long* __restrict__ base,
+                                       const int* __restrict__ local_off, int nv, long long item,
+                                       int* local) {
+    const int nblk = (nv + 255) >> 8;
+    int lo = 0, hi = nblk;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int rel = (int)(item - base[lo]);
+    int a = lo << 8, e = min(nv, a + 256);
+    while (e - a > 1) {
+        const int mid = (a + e) >> 1;
+        if (local_off[mid] <= rel) a = mid; else e = mid;
+    }
+    *local = rel - local_off[a];
+    return a;
 }
 
+__device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// Each wave takes chunks of 64 consecutive tile items.  Lane k first finds
+// the triangle and tile of item k of the chunk (64 searches in flight at
+// once); the wave then walks the chunk's items, one lane per texel of the 8x8
+// tile, with the item's triangle coefficients in scalar registers.  Inside
+// the walk nothing waits on vector memory: the depth update is a
+// fire-and-forget integer atomicMin.
+//
+// All coverage arithmetic is float64 on exact integers: snapped coordinates
+// lie in the guard band, below 2^26 in magnitude for targets up to 16384
+// texels, so every product and partial sum of E_k is an integer under 2^53
+// and each E_k is exact (what 64-bit integer arithmetic gives).  The depth
+// quotient num / area is rounded correctly with one fused correction of
+// num * (1 / area) (Markstein's theorem: the reciprocal is rounded to nearest
+// and the first quotient is within one ulp), so it equals the IEEE division.
 __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ setup,
+                                                const TriCoef* __restrict__ coef,
                                                 const long long* __restrict__ base,
                                                 const int* __restrict__ local_off, int n_tris,
                                                 RasterPasses P) {
     const int lane = threadIdx.x & 63;
     const int nv = P.npass * n_tris;             // virtual triangles
-    const long long wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const long long nwaves = gridDim.x * (blockDim.x >> 6);
     const long long total = tri_start(base, local_off, nv, nv);
-    const long long per = (total + nwaves - 1) / nwaves;
-    const long long begin = wave * per;
-    const long long end = min(total, begin + per);
-    if (begin >= end) return;
-    // largest v with start(v) <= begin
-    int lo = 0, hi = nv;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (tri_start(base, local_off, mid, nv) <= begin) lo = mid; else hi = mid;
-    }
-    int v = lo;
-    long long v_begin = tri_start(base, local_off, v, nv);
-    long long v_end = tri_start(base, local_off, v + 1, nv);
-    for (long long item = begin; item < end; ++item) {
-        while (v_end <= item) {
-            ++v;
-            v_begin = v_end;
-            v_end = tri_start(base, local_off, v + 1, nv);
+    const long long nchunks = (total + 63) >> 6;
+    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+    const int w0 = P.p[0].w, h0 = P.p[0].h, w1 = P.p[1].w, h1 = P.p[1].h;
+    const bool k0 = P.p[0].key64, k1 = P.p[1].key64;
+    void* const o0 = P.p[0].out;
+    void* const o1 = P.p[1].out;
+    const int lx = lane & 7, ly = lane >> 3;
+    for (long long chunk = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); chunk < nchunks;
+         chunk += nwaves) {
+        const long long item = (chunk << 6) + lane;
+        int v = 0, tx = 0, ty = 0;
+        if (item < total) {
+            int local;
+            v = find_tri(base, local_off, nv, item, &local);
+            const int ntx = setup[v].ntx;
+            tx = setup[v].tx0 + local % ntx;
+            ty = setup[v].ty0 + local / ntx;
         }
-        const int pass = v >= n_tris ? 1 : 0;
-        const int t = v - pass * n_tris;
-        const RasterPass& rp = pass ? P.p[1] : P.p[0];
-        const TriSetup s = setup[v];
-        const int local = (int)(item - v_begin);
-        const int tx = s.tx0 + local % s.ntx;
-        const int ty = s.ty0 + local / s.ntx;
-        const int i = tx * 8 + (lane & 7);
-        const int j = ty * 8 + (lane >> 3);
-        if (i >= rp.w || j >= rp.h) continue;
-        const int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
-        const int64_t X0 = s.x[0], X1 = s.x[1], X2 = s.x[2];
-        const int64_t Y0 = s.y[0], Y1 = s.y[1], Y2 = s.y[2];
-        // E_k: edge opposite vertex k, positive inside a CCW triangle
-        const int64_t e0 = (X2 - X1) * (py - Y1) - (Y2 - Y1) * (px - X1);
-        const int64_t e1 = (X0 - X2) * (py - Y2) - (Y0 - Y2) * (px - X2);
-        const int64_t e2 = (X1 - X0) * (py - Y0) - (Y1 - Y0) * (px - X0);
-        const bool in0 = e0 > 0 || (e0 == 0 && edge_inclusive(X2 - X1, Y2 - Y1));
-        const bool in1 = e1 > 0 || (e1 == 0 && edge_inclusive(X0 - X2, Y0 - Y2));
-        const bool in2 = e2 > 0 || (e2 == 0 && edge_inclusive(X1 - X0, Y1 - Y0));
-        if (!(in0 && in1 && in2)) continue;
-        double num = (double)e0 * (double)s.z[0];
-        num = num + (double)e1 * (double)s.z[1];
-        num = num + (double)e2 * (double)s.z[2];
-        const float d = (float)(num / (double)s.area);
-        if (!(d >= 0.0f && d <= 1.0f)) continue;
-        uint32_t bits = __float_as_uint(d);
-        if ((bits & 0x7FFFFFFFu) == 0) bits = 0;  // -0 -> +0
-        const size_t k = (size_t)j * (size_t)rp.w + (size_t)i;
-        // Stored values only ever decrease, so a plain read that is already
-        // <= the new key proves the atomic would change nothing.
-        if (rp.key64) {
-            unsigned long long* o = reinterpret_cast<unsigned long long*>(rp.out) + k;
-            const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
-            if (*o > key) atomicMin(o, key);
-        } else {
-            uint32_t* o = reinterpret_cast<uint32_t*>(rp.out) + k;
-            if (*o > bits) atomicMin(o, bits);
+        const int cnt = (int)min((long long)64, total - (chunk << 6));
+        for (int k = 0; k < cnt; ++k) {
+            const int vk = bcast(v, k);
+            const bool pass = vk >= n_tris;
+            const int t = vk - (pass ? n_tris : 0);
+            const int rw = pass ? w1 : w0, rh = pass ? h1 : h0;
+            const int i = bcast(tx, k) * 8 + lx;
+            const int j = bcast(ty, k) * 8 + ly;
+            if (i >= rw || j >= rh) continue;
+            const TriCoef& c = coef[vk];
+            const double px = (double)(256 * i + 128), py = (double)(256 * j + 128);
+            const double e0 = fma(c.dx[0], py, fma(-c.dy[0], px, c.c[0]));
+            const double e1 = fma(c.dx[1], py, fma(-c.dy[1], px, c.c[1]));
+            const double e2 = fma(c.dx[2], py, fma(-c.dy[2], px, c.c[2]));
+            const int incl = c.incl;
+            const bool in0 = (e0 > 0.0) | ((e0 == 0.0) & ((incl & 1) != 0));
+            const bool in1 = (e1 > 0.0) | ((e1 == 0.0) & ((incl & 2) != 0));
+            const bool in2 = (e2 > 0.0) | ((e2 == 0.0) & ((incl & 4) != 0));
+            if (!(in0 & in1 & in2)) continue;
+            double num = e0 * c.z[0];
+            num = num + e1 * c.z[1];
+            num = num + e2 * c.z[2];
+            const double q0 = num * c.inv_area;
+            const double q = fma(fma(-q0, c.area, num), c.inv_area, q0);
+            const float d = (float)q;
+            if (!(d >= 0.0f && d <= 1.0f)) continue;
+            uint32_t bits = __float_as_uint(d);
+            if ((bits & 0x7FFFFFFFu) == 0) bits = 0;  // -0 -> +0
+            const size_t o = (size_t)j * (size_t)rw + (size_t)i;
+            if (pass ? k1 : k0) {
+                const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
+                atomicMin(reinterpret_cast<unsigned long long*>(pass ? o1 : o0) + o, key);
+            } else {
+                atomicMin(reinterpret_cast<uint32_t*>(pass ? o1 : o0) + o, bits);
+            }
         }
     }
 }
@@ -435,8 +506,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t raster_workspace_bytes(int n_tris) {
     const size_t nv = 2 * (size_t)n_tris, nblk = (nv + 255) / 256;
-    return align256(nv * sizeof(TriSetup)) + align256(nv * 4) + align256(nblk * 4) +
-           align256((nblk + 1) * 8);
+    return align256(nv * sizeof(TriSetup)) + align256(nv * sizeof(TriCoef)) + align256(nv * 4) +
+           align256(nblk * 4) + align256((nblk + 1) * 8);
 }
 
 hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws, hipStream_t s) {
@@ -450,33 +521,32 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
         f[k].pattern = rp.key64 ? kEmptyKey : (((unsigned long long)kEmptyDepth << 32) | kEmptyDepth);
         most = max(most, f[k].bytes);
     }
-    {
-        TraceScope ts("clear", sfx, s);
-        const int blocks = (int)min((size_t)2048, (most / 16 + 255) / 256 + 1);
-        k_fill2<<<blocks, 256, 0, s>>>(f[0], f[1]);
-    }
-    if (n_tris == 0) return hipGetLastError();
     const int nv = P.npass * n_tris;
     const int nblk = (nv + 255) / 256;
     char* wsb = reinterpret_cast<char*>(ws);
     TriSetup* setup = reinterpret_cast<TriSetup*>(wsb);
     wsb += align256((size_t)nv * sizeof(TriSetup));
+    TriCoef* coef = reinterpret_cast<TriCoef*>(wsb);
+    wsb += align256((size_t)nv * sizeof(TriCoef));
     int* local_off = reinterpret_cast<int*>(wsb);
     wsb += align256((size_t)nv * 4);
     int* block_sum = reinterpret_cast<int*>(wsb);
     wsb += align256((size_t)nblk * 4);
     long long* base = reinterpret_cast<long long*>(wsb);
     {
-        TraceScope ts("tri_setup", sfx, s);
-        k_tri_setup<<<nblk, 256, 0, s>>>(tris, n_tris, P, setup, local_off, block_sum);
+        TraceScope ts("setup+clear", sfx, s);
+        const int fill_blocks = (int)min((size_t)1024, (most / 16 + 255) / 256 + 1);
+        k_tri_setup<<<nblk + fill_blocks, 256, 0, s>>>(tris, n_tris, P, setup, coef, local_off, block_sum, nblk,
+                                                       f[0], f[1]);
     }
+    if (n_tris == 0) return hipGetLastError();
     {
         TraceScope ts("tile_scan", sfx, s);
         k_block_scan<<<1, kScanThreads, 0, s>>>(block_sum, nblk, base);
     }
     {
         TraceScope ts("raster", sfx, s);
-        k_raster<<<kRasterBlocks, 256, 0, s>>>(setup, base, local_off, n_tris, P);
+        k_raster<<<kRasterBlocks, 256, 0, s>>>(setup, coef, base, local_off, n_tris, P);
     }
     return hipGetLastError();
 }

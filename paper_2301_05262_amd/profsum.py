@@ -1,0 +1,139 @@
+"""Summaries of rocprofv3 output for the `profiles/` folder, and the HBM
+traffic figures the benchmark reports.
+
+  python -m paper_2301_05262_amd.profsum stats <run_kernel_stats.csv> [title]
+      markdown table of per-kernel calls / average / total time
+  python -m paper_2301_05262_amd.profsum traffic <fetch_dir> <write_dir> [title]
+      per-kernel HBM bytes per dispatch from one FETCH_SIZE and one WRITE_SIZE
+      counter run (rocprofv3 --pmc ... --output-format csv), each scaled by what
+      the same counter reads for the plain 256 MiB device copy that
+      `bench.py --calib-copy 1` issues; ends with a machine-readable line
+
+The traffic figures are tied to the library sources they were measured on
+(a hash of csrc/): `recorded_traffic()` returns nothing once those differ.
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CALIB_BYTES = 256 << 20          # the calibration copy: 256 MiB read, 256 MiB written
+TRAFFIC_TAG = "traffic-json:"
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if p.endswith((".hip", ".h")):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _strip_args(k):
+    """Drop the trailing function parameter list '( ... )' (and any '[clone ...]')."""
+    k = re.sub(r"\s*\[clone [^\]]*\]$", "", k.strip())
+    if not k.endswith(")"):
+        return k
+    depth = 0
+    for i in range(len(k) - 1, -1, -1):
+        if k[i] == ")":
+            depth += 1
+        elif k[i] == "(":
+            depth -= 1
+            if depth == 0:
+                return k[:i]
+    return k
+
+
+def short_name(k):
+    """Kernel symbol -> readable name with template arguments."""
+    k = _strip_args(k)
+    k = re.sub(r"\(nsm::Dt\)(\d)", lambda m: ["f32", "bf16", "f16"][int(m.group(1))], k)
+    k = re.sub(r"\(nsm::OutMode\)(\d)", lambda m: ["Store", "Pool", "Head", "Linear"][int(m.group(1))], k)
+    k = re.sub(r"\(nsm::PMode\)(\d)", lambda m: ["Store", "PoolOnly", "PoolSkip", "Head"][int(m.group(1))], k)
+    k = k.replace("nsm::(anonymous namespace)::", "").replace("nsm::ck::", "").replace("nsm::", "")
+    k = re.sub(r"^void ", "", k)
+    return k
+
+
+def stats_table(path, title="kernel trace"):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"### {title}", "", "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def _counter(dirname, name):
+    """{kernel short name: mean counter value per dispatch} and the calibration copy value."""
+    vals = {}
+    for f in glob.glob(os.path.join(dirname, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != name:
+                continue
+            vals.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic_table(fetch_dir, write_dir, title="HBM traffic"):
+    fe, wr = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
+    # the calibration copy is the largest copy dispatch in the run
+    copies = [k for k in fe if "copyBuffer" in k or "copy" in k.lower()]
+    cf = max((max(fe[k]) for k in copies), default=0.0)
+    cw = max((max(wr.get(k, [0.0])) for k in copies), default=0.0)
+    if cf <= 0 or cw <= 0:
+        raise SystemExit("no calibration copy found in the counter runs")
+    sf, sw = CALIB_BYTES / (cf * 1024), CALIB_BYTES / (cw * 1024)
+    out = [f"### {title}", "",
+           f"Counters are KiB per dispatch; scale factors from the 256 MiB calibration copy: "
+           f"FETCH_SIZE x{sf:.3f}, WRITE_SIZE x{sw:.3f}.", "",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB (scaled) |", "|---|---|---|---|---|"]
+    rec = {}
+    for k in sorted(fe, key=lambda k: -sum(fe[k]) / len(fe[k])):
+        if k in copies or k not in wr:
+            continue
+        f_ = sum(fe[k]) / len(fe[k])
+        w_ = sum(wr[k]) / len(wr[k])
+        mb = (f_ * sf + w_ * sw) * 1024 / 1e6
+        out.append(f"| `{k}` | {len(fe[k])} | {f_:.1f} | {w_:.1f} | {mb:.2f} |")
+        rec[k] = {"fetch_kib": f_, "write_kib": w_, "bytes": mb * 1e6}
+    out += ["", TRAFFIC_TAG + " " + json.dumps({"source": source_hash(), "scale": [sf, sw], "kernels": rec})]
+    return "\n".join(out)
+
+
+def recorded_traffic(md_path):
+    """Kernel -> measured HBM bytes per dispatch from a committed summary, or {}
+    when the summary is missing or the library sources changed since."""
+    try:
+        for line in open(md_path):
+            if line.startswith(TRAFFIC_TAG):
+                d = json.loads(line[len(TRAFFIC_TAG):])
+                if d.get("source") != source_hash():
+                    return {}
+                return {k: v["bytes"] for k, v in d["kernels"].items()}
+    except OSError:
+        pass
+    return {}
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "stats":
+        print(stats_table(argv[1], *(argv[2:3])))
+    elif len(argv) >= 3 and argv[0] == "traffic":
+        print(traffic_table(argv[1], argv[2], *(argv[3:4])))
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
