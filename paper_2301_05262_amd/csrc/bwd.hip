@@ -180,7 +180,8 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     __shared__ __attribute__((aligned(16))) float dzt[TPX * CO];
     __shared__ __attribute__((aligned(16))) float lowt[LowTile<Dt::F32, CU, TH>::SIZE];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform in the wave: keep it in a scalar register
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
     // per owned column fragment: LDS offset of this lane's (tap, channel), -1 bias column, -2 padding
     int boff[FPW];

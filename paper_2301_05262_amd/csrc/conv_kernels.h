@@ -126,6 +126,41 @@ __device__ __forceinline__ void unpack_block(const u32x4& r, float* v) {
     for (int e = 0; e < EPB; ++e) v[e] = to_f(t[e]);
 }
 
+// Raw buffer access: a resource over [base, base + 2 GiB) in scalar registers
+// and a byte offset split into a per-lane part and a scalar part, so a load
+// or store whose scalar part is a compile-time constant costs no vector ALU
+// for its address.  Reads past the range return zero.
+constexpr int kBufWord3 = 0x00020000;   // raw 32-bit data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, kBufWord3);
+}
+__device__ __forceinline__ u32x4 buf_load16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+
+// Four consecutive channels (converted to T) as one 8- or 16-byte buffer store.
+template <typename T>
+__device__ __forceinline__ void buf_store4(__amdgpu_buffer_rsrc_t r, int voff, int soff, const f32x4& v) {
+    T t4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t4[e] = from_f<T>(v[e]);
+    if constexpr (sizeof(T) == 4) {
+        u32x4 q;
+        __builtin_memcpy(&q, t4, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(q, r, voff, soff, 0);
+    } else {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        u32x2 q;
+        __builtin_memcpy(&q, t4, 8);
+        __builtin_amdgcn_raw_buffer_store_b64(q, r, voff, soff, 0);
+    }
+}
+
+// Sigmoid with the hardware reciprocal (within 1 ulp of 1 / (1 + e^-x)).
+__device__ __forceinline__ float sigmoid_fast(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+}
+
 // Global -> LDS copy of N1 + N2 16-byte items by the whole block: every load
 // of a thread is issued before its first LDS store, so the tile costs about
 // one memory latency instead of one per item.  src(idx) returns the item,
@@ -153,6 +188,85 @@ __device__ __forceinline__ void copy_batched(S1 src1, D1 dst1, S2 src2, D2 dst2)
     for (int k = 0; k < P2; ++k) {
         const int idx = threadIdx.x + k * kThreads;
         if (idx < N2) dst2(idx, v2[k]);
+    }
+}
+
+// Row-structured variant for tiles whose rows are contiguous runs of K
+// 16-byte chunks in global memory: thread t copies chunk t % K of rows
+// t / K, t / K + R, ... (R = 256 / K rows per pass), so the only per-item
+// index arithmetic is one division at the start and the per-pass offsets are
+// uniform.  ld(r, k) loads chunk k of row r, st(r, k, v) stores it; both
+// tiles' loads are all issued before the first store.
+// Rows longer than the block are split into NS equal pieces (virtual rows).
+template <int ROWS1, int K1, int ROWS2, int K2, class L1, class S1, class L2, class S2>
+__device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2);
+
+__host__ __device__ constexpr int row_pieces(int k) {
+    int ns = (k + kThreads - 1) / kThreads;
+    while (k % ns != 0) ++ns;
+    return ns;
+}
+
+template <int K>
+struct RowSplit {
+    static constexpr int NS = row_pieces(K);      // fewest equal pieces of at most kThreads chunks
+    static constexpr int KP = K / NS;
+};
+
+template <int ROWS1, int K1, int ROWS2, int K2, class L1, class S1, class L2, class S2>
+__device__ __forceinline__ void copy_rows2_split(L1 ld1, S1 st1, L2 ld2, S2 st2) {
+    using A = RowSplit<K1>;
+    using B = RowSplit<K2>;
+    auto l1 = [&](int vr, int k) { return ld1(vr / A::NS, (vr % A::NS) * A::KP + k); };
+    auto s1 = [&](int vr, int k, const u32x4& v) { st1(vr / A::NS, (vr % A::NS) * A::KP + k, v); };
+    auto l2 = [&](int vr, int k) { return ld2(vr / B::NS, (vr % B::NS) * B::KP + k); };
+    auto s2 = [&](int vr, int k, const u32x4& v) { st2(vr / B::NS, (vr % B::NS) * B::KP + k, v); };
+    copy_rows2<ROWS1 * A::NS, A::KP, ROWS2 * B::NS, B::KP>(l1, s1, l2, s2);
+}
+
+template <int ROWS1, int K1, int ROWS2, int K2, class L1, class S1, class L2, class S2>
+__device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2) {
+    if constexpr (K1 > kThreads || K2 > kThreads) {
+        copy_rows2_split<ROWS1, K1, ROWS2, K2>(ld1, st1, ld2, st2);
+        return;
+    } else {
+    constexpr int R1 = kThreads / K1, R2 = kThreads / K2;
+    constexpr int P1 = (ROWS1 + R1 - 1) / R1, P2 = (ROWS2 + R2 - 1) / R2;
+    const int k1 = threadIdx.x % K1, r1 = threadIdx.x / K1;
+    const int k2 = threadIdx.x % K2, r2 = threadIdx.x / K2;
+    // loads are unconditional (rows clamped into the tile) so that no value
+    // has to be merged across branches; only the stores are predicated
+    u32x4 v1[P1], v2[P2];
+#pragma unroll
+    for (int p = 0; p < P1; ++p) v1[p] = ld1(min(r1 + p * R1, ROWS1 - 1), k1);
+#pragma unroll
+    for (int p = 0; p < P2; ++p) v2[p] = ld2(min(r2 + p * R2, ROWS2 - 1), k2);
+#pragma unroll
+    for (int p = 0; p < P1; ++p)
+        if (r1 < R1 && r1 + p * R1 < ROWS1) st1(r1 + p * R1, k1, v1[p]);
+#pragma unroll
+    for (int p = 0; p < P2; ++p)
+        if (r2 < R2 && r2 + p * R2 < ROWS2) st2(r2 + p * R2, k2, v2[p]);
+    }
+}
+
+// One tile only.
+template <int ROWS, int K, class L, class S>
+__device__ __forceinline__ void copy_rows1(L ld, S st) {
+    if constexpr (K > kThreads) {
+        using A = RowSplit<K>;
+        auto l = [&](int vr, int k) { return ld(vr / A::NS, (vr % A::NS) * A::KP + k); };
+        auto s = [&](int vr, int k, const u32x4& v) { st(vr / A::NS, (vr % A::NS) * A::KP + k, v); };
+        copy_rows1<ROWS * A::NS, A::KP>(l, s);
+    } else {
+        constexpr int R = kThreads / K, P = (ROWS + R - 1) / R;
+        const int k = threadIdx.x % K, r0 = threadIdx.x / K;
+        u32x4 v[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) v[p] = ld(min(r0 + p * R, ROWS - 1), k);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (r0 < R && r0 + p * R < ROWS) st(r0 + p * R, k, v[p]);
     }
 }
 
@@ -188,48 +302,69 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     static_assert(!SUM || CS == CU, "a sum skip needs equal channel counts");
     constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
     constexpr int NCH_S = CSP / EPB, NCH_U = CU / EPB;
-    // phase 1: same-resolution channels, and the low-res source rows
-    auto skip_src = [&](int idx) -> u32x4 {
-        const int pix = idx / (NCH_S > 0 ? NCH_S : 1), ch = idx - pix * NCH_S;
-        const int ty = pix / WP, tx = pix - ty * WP;
-        const int y = y0 + ty - 1, x = x0 + tx - 1;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (y >= 0 && y < h && x >= 0 && x < w) {
-            const size_t p = ((size_t)n * h + y) * w + x;
-            if constexpr (IN_F32) {
-                const float* src = reinterpret_cast<const float*>(in) + p * CS;
-                float f[EPB];
+    // phase 1: same-resolution channels, and the low-res source rows.
+    // Buffer offsets are relative to each tile's first (halo) pixel, taken
+    // at clamped coordinates; pixels outside the image then read as zero.
+    constexpr int SZ_IN = IN_F32 ? 4 : (int)sizeof(T);
+    const char* sbase = reinterpret_cast<const char*>(in) + ((((long long)n * h + y0 - 1) * w + x0 - 1) * CS) * SZ_IN;
+    const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase);
+    const int srow = w * CS * SZ_IN;
+    auto skip_ld = [&](int r, int k) -> u32x4 {
+        const int c = k / (NCH_S > 0 ? NCH_S : 1), ch = k - c * NCH_S;
+        const int y = y0 + r - 1, x = x0 + c - 1;
+        const bool ok = y >= 0 && y < h && x >= 0 && x < w;
+        const int yr = min(max(y, 0), h - 1) - (y0 - 1), xr = min(max(x, 0), w - 1) - (x0 - 1);
+        const int voff = yr * srow + xr * (CS * SZ_IN);
+        u32x4 v;
+        if constexpr (IN_F32) {
+            // float32 features: EPB channels of block ch, zero past CS
+            float f[EPB];
 #pragma unroll
-                for (int e = 0; e < EPB; ++e) {
-                    const int c = ch * EPB + e;
-                    f[e] = (c < CS) ? src[c] : 0.0f;
+            for (int e = 0; e < EPB; e += 2) {
+                const int c0 = ch * EPB + e;
+                if (c0 + 1 < CS) {
+                    typedef float f32x2 __attribute__((ext_vector_type(2)));
+                    const f32x2 q = __builtin_bit_cast(
+                        f32x2, __builtin_amdgcn_raw_buffer_load_b64(sr, voff + c0 * 4, 0, 0));
+                    f[e] = q[0];
+                    f[e + 1] = q[1];
+                } else {
+                    f[e] = (c0 < CS) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sr, voff + c0 * 4, 0, 0))
+                                     : 0.0f;
+                    f[e + 1] = 0.0f;
                 }
-                v = pack_block<D>(f);
-            } else {
-                v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(in) + p * CS + ch * EPB);
             }
+            v = pack_block<D>(f);
+        } else {
+            v = buf_load16(sr, voff + ch * 16, 0);
         }
-        return v;
+        return ok ? v : u32x4{0u, 0u, 0u, 0u};
     };
-    auto skip_dst = [&](int idx, const u32x4& v) {
-        const int pix = idx / (NCH_S > 0 ? NCH_S : 1), ch = idx - pix * NCH_S;
-        *reinterpret_cast<u32x4*>(&tile[pix * CST + ch * EPB]) = v;
+    auto skip_st = [&](int r, int k, const u32x4& v) {
+        const int c = k / (NCH_S > 0 ? NCH_S : 1), ch = k - c * NCH_S;
+        *reinterpret_cast<u32x4*>(&tile[(r * WP + c) * CST + ch * EPB]) = v;
     };
-    constexpr int NLOW = CU > 0 ? LT::LH * LT::LW * NCH_U : 0;
     const int hl = h >> 1, wl = w >> 1;
     const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
-    const T* lo = reinterpret_cast<const T*>(low) + (size_t)n * hl * wl * CU;
-    auto low_src = [&](int idx) -> u32x4 {
-        const int pix = idx / (NCH_U > 0 ? NCH_U : 1), ch = idx - pix * NCH_U;
-        const int r = pix / LT::LW, c = pix - r * LT::LW;
-        const int gy = min(max(ly0 + r, 0), hl - 1), gx = min(max(lx0 + c, 0), wl - 1);
-        return *reinterpret_cast<const u32x4*>(lo + ((size_t)gy * wl + gx) * CU + ch * EPB);
+    const char* lbase = reinterpret_cast<const char*>(low) +
+                        ((((long long)n * hl + ly0) * wl + lx0) * CU) * (long long)sizeof(T);
+    const __amdgpu_buffer_rsrc_t lr = buf_rsrc(lbase);
+    const int lrow = wl * CU * (int)sizeof(T);
+    auto low_ld = [&](int r, int k) -> u32x4 {
+        const int c = k / (NCH_U > 0 ? NCH_U : 1), ch = k - c * NCH_U;
+        const int gy = min(max(ly0 + r, 0), hl - 1) - ly0, gx = min(max(lx0 + c, 0), wl - 1) - lx0;
+        return buf_load16(lr, gy * lrow + gx * (CU * (int)sizeof(T)) + ch * 16, 0);
     };
-    auto low_dst = [&](int idx, const u32x4& v) {
-        const int pix = idx / (NCH_U > 0 ? NCH_U : 1), ch = idx - pix * NCH_U;
-        *reinterpret_cast<u32x4*>(&lowt[pix * LT::LCST + ch * EPB]) = v;
+    auto low_st = [&](int r, int k, const u32x4& v) {
+        const int c = k / (NCH_U > 0 ? NCH_U : 1), ch = k - c * NCH_U;
+        *reinterpret_cast<u32x4*>(&lowt[(r * LT::LW + c) * LT::LCST + ch * EPB]) = v;
     };
-    copy_batched<NPIX * NCH_S, NLOW>(skip_src, skip_dst, low_src, low_dst);
+    if constexpr (NCH_S > 0 && CU > 0)
+        copy_rows2<TH + 2, WP * NCH_S, LT::LH, LT::LW * NCH_U>(skip_ld, skip_st, low_ld, low_st);
+    else if constexpr (NCH_S > 0)
+        copy_rows1<TH + 2, WP * NCH_S>(skip_ld, skip_st);
+    else if constexpr (CU > 0)
+        copy_rows1<LT::LH, LT::LW * NCH_U>(low_ld, low_st);
     if constexpr (CU > 0) {
         __syncthreads();
         // phase 2: upsampled channels from the staged rows
@@ -352,9 +487,11 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
     load_halo_tile<D, IN_F32, CS, CU, CST, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     // ---------------- main loop
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform in the wave: keep it in a scalar register
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int px = lane & 15, g = lane >> 4;
-    const u32x4* wpk = reinterpret_cast<const u32x4*>(a.wpk);
+    const __amdgpu_buffer_rsrc_t wr = buf_rsrc(a.wpk);
+    const int wl16 = lane * 16;
     f32x4 acc[MF][NF];
 #pragma unroll
     for (int m = 0; m < MF; ++m)
@@ -365,7 +502,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
     for (int q = 0; q < NKG; ++q) {
         u32x4 wf[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) wf[f] = wpk[(f * NKG + q) * 64 + lane];
+        for (int f = 0; f < NF; ++f) wf[f] = buf_load16(wr, wl16, (f * NKG + q) * 1024);
         int b = 4 * q + g;
         if (b >= NB) b = NB - 1;               // padding k: weights are zero there
         const int tap = b / BPT, cb = b - tap * BPT;

@@ -158,40 +158,33 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     const int x0 = (lt % gx + 1) * kTW, y0 = ((lt / gx) % gy + 1) * TH, n = lt / (gx * gy);
 
     // ---------------- prologue: skip tile (split by column parity) and low tile
+    // Interior tiles read only in-image pixels: skip rows y0-1 .. y0+TH and
+    // columns x0-1 .. x0+32, low rows y0/2-1 .. y0/2+TH/2 and columns
+    // x0/2-1 .. x0/2+16, all inside the image (and no clamping is needed).
     {
-        const T* in = reinterpret_cast<const T*>(a.in);
-        const T* lo = reinterpret_cast<const T*>(a.low) + (size_t)n * hl * wl * CU;
-        const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
-        auto skip_src = [&](int idx) -> u32x4 {
-            const int cb = idx % G::BPT_S, pix = idx / G::BPT_S;
-            const int r = pix / 34, c = pix - r * 34;
-            const int y = y0 + r - 1, x = x0 + c - 1;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (y >= 0 && y < h && x >= 0 && x < w)
-                v = *reinterpret_cast<const u32x4*>(in + (((size_t)n * h + y) * w + x) * CS + cb * EPB);
-            return v;
-        };
-        auto skip_dst = [&](int idx, const u32x4& v) {
-            const int cb = idx % G::BPT_S, pix = idx / G::BPT_S;
-            const int r = pix / 34, c = pix - r * 34;
+        using TT = typename DT<D>::T;
+        constexpr int KS = 34 * G::BPT_S, KL = UT::LC * G::BPT_U;   // 16-byte chunks per tile row
+        const TT* sbase = reinterpret_cast<const TT*>(a.in) + (((size_t)n * h + y0 - 1) * w + x0 - 1) * CS;
+        const TT* lbase = reinterpret_cast<const TT*>(a.low) + (((size_t)n * hl + (y0 >> 1) - 1) * wl + (x0 >> 1) - 1) * CU;
+        const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase), lr = buf_rsrc(lbase);
+        const int srow = w * CS * (int)sizeof(TT), lrow = wl * CU * (int)sizeof(TT);
+        auto skip_ld = [&](int r, int k) -> u32x4 { return buf_load16(sr, r * srow + k * 16, 0); };
+        auto skip_st = [&](int r, int k, const u32x4& v) {
+            const int c = k / G::BPT_S, cb = k - c * G::BPT_S;
             *reinterpret_cast<u32x4*>(&skip[((r * 2 + (c & 1)) * UT::SC + (c >> 1)) * CSTS + cb * EPB]) = v;
         };
-        auto low_src = [&](int idx) -> u32x4 {
-            const int cb = idx % G::BPT_U, pix = idx / G::BPT_U;
-            const int r = pix / UT::LC, c = pix - r * UT::LC;
-            const int gyl = min(max(ly0 + r, 0), hl - 1), gxl = min(max(lx0 + c, 0), wl - 1);
-            return *reinterpret_cast<const u32x4*>(lo + ((size_t)gyl * wl + gxl) * CU + cb * EPB);
+        auto low_ld = [&](int r, int k) -> u32x4 { return buf_load16(lr, r * lrow + k * 16, 0); };
+        auto low_st = [&](int r, int k, const u32x4& v) {
+            const int c = k / G::BPT_U, cb = k - c * G::BPT_U;
+            *reinterpret_cast<u32x4*>(&lowt[(r * UT::LC + c) * CSTU + cb * EPB]) = v;
         };
-        auto low_dst = [&](int idx, const u32x4& v) {
-            const int cb = idx % G::BPT_U, pix = idx / G::BPT_U;
-            *reinterpret_cast<u32x4*>(&lowt[pix * CSTU + cb * EPB]) = v;
-        };
-        copy_batched<UT::SR * 34 * G::BPT_S, UT::LR * UT::LC * G::BPT_U>(skip_src, skip_dst, low_src, low_dst);
+        copy_rows2<UT::SR, KS, UT::LR, KL>(skip_ld, skip_st, low_ld, low_st);
     }
     __syncthreads();
 
     // ---------------- main loop
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform in the wave: keep it in a scalar register
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int j = lane & 15, g = lane >> 4;
     const int py = wave & 1, half = wave >> 1;
     f32x4 acc[RW][2][NF];
@@ -203,12 +196,13 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
             for (int f = 0; f < NF; ++f) acc[m][p][f] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // skip channels: ordinary 3x3 taps over the full-resolution tile
-    const u32x4* wsk = reinterpret_cast<const u32x4*>(wup);
+    const __amdgpu_buffer_rsrc_t wr = buf_rsrc(wup);
+    const int wl16 = lane * 16;
 #pragma unroll
     for (int q = 0; q < G::NKG_S; ++q) {
         u32x4 wf[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) wf[f] = wsk[(f * G::NKG_S + q) * 64 + lane];
+        for (int f = 0; f < NF; ++f) wf[f] = buf_load16(wr, wl16, (f * G::NKG_S + q) * 1024);
         int b = 4 * q + g;
         if (b >= G::NB_S) b = G::NB_S - 1;     // padding k: weights are zero there
         const int tap = b / G::BPT_S, cb = b - tap * G::BPT_S;
@@ -227,14 +221,15 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
         }
     }
     // upsampled channels: phase kernels over the low-resolution tile
-    const u32x4* wlo = wsk + (size_t)NF * G::NKG_S * 64;
+    constexpr int WLO = NF * G::NKG_S * 1024;                  // byte offset of the phase packs
+    const int wph = WLO + py * 2 * NF * G::NKG_U * 1024;        // this wave's row phase
 #pragma unroll
     for (int q = 0; q < G::NKG_U; ++q) {
         u32x4 w0[NF], w1[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            w0[f] = wlo[(((py * 2 + 0) * NF + f) * G::NKG_U + q) * 64 + lane];
-            w1[f] = wlo[(((py * 2 + 1) * NF + f) * G::NKG_U + q) * 64 + lane];
+            w0[f] = buf_load16(wr, wl16, wph + (f * G::NKG_U + q) * 1024);
+            w1[f] = buf_load16(wr, wl16, wph + ((NF + f) * G::NKG_U + q) * 1024);
         }
         int b = 4 * q + g;
         if (b >= G::NB_U) b = G::NB_U - 1;
@@ -280,52 +275,67 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
                 hw[f][e] = (co < CO) ? a.head_w[co] : 0.0f;
             }
         const float hb = a.head_w[CO];
+        // s[m][p]: logit of pixel (row m, column 2j + p), complete in every
+        // lane group after the two cross-group sums
+        float s[RW][2];
 #pragma unroll
         for (int m = 0; m < RW; ++m)
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const int y = y0 + py + 2 * (RW * half + m), x = x0 + 2 * j + p;
-                const bool ok = y < h && x < w;
-                const size_t pi = ((size_t)n * h + y) * w + x;
-                float s = 0.0f;
+                float v = 0.0f;
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) s += hw[f][e] * acc[m][p][f][e];
-                s += __shfl_xor(s, 16);
-                s += __shfl_xor(s, 32);
-                if (ok && g == 0) {
-                    const float logit = s + hb;
-                    a.vis[pi] = 1.0f / (1.0f + __expf(-logit));
-                    if (a.logits) a.logits[pi] = logit;
-                }
-                if (ok && a.act_out) {
+                    for (int e = 0; e < 4; ++e) v += hw[f][e] * acc[m][p][f][e];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                s[m][p] = v + hb;
+            }
+        // lane group g finishes rows m with m % 4 == g: one sigmoid per pixel
+        // in the wave, and two adjacent pixels per 8-byte store
+#pragma unroll
+        for (int m0 = 0; m0 < RW; m0 += 4) {
+            if (m0 + g < RW) {
+                float l0 = s[m0][0], l1 = s[m0][1];
+#pragma unroll
+                for (int k = 1; k < 4; ++k)
+                    if (m0 + k < RW && g == k) { l0 = s[m0 + k][0]; l1 = s[m0 + k][1]; }
+                const int y = y0 + py + 2 * (RW * half + m0 + g), x = x0 + 2 * j;
+                const size_t pi = ((size_t)n * h + y) * w + x;
+                *reinterpret_cast<float2*>(a.vis + pi) = make_float2(sigmoid_fast(l0), sigmoid_fast(l1));
+                if (a.logits) *reinterpret_cast<float2*>(a.logits + pi) = make_float2(l0, l1);
+            }
+        }
+        if (a.act_out) {
+#pragma unroll
+            for (int m = 0; m < RW; ++m)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const int y = y0 + py + 2 * (RW * half + m), x = x0 + 2 * j + p;
+                    const size_t pi = ((size_t)n * h + y) * w + x;
 #pragma unroll
                     for (int f = 0; f < NF; ++f) {
                         const int co = f * 16 + 4 * g;
                         if (co < CO) *reinterpret_cast<f32x4*>(a.act_out + pi * CO + co) = acc[m][p][f];
                     }
                 }
-            }
+        }
     } else {
-        T* out = reinterpret_cast<T*>(a.out);
+        // interior tile: every pixel is in the image; offsets relative to the
+        // tile's first pixel, the row step in a scalar register
+        static_assert(CO % 16 == 0, "stored decoder stages fill whole 16-channel fragments");
+        constexpr int SZ = (int)sizeof(T);
+        const __amdgpu_buffer_rsrc_t orc =
+            buf_rsrc(reinterpret_cast<T*>(a.out) + (((size_t)n * h + y0) * w + x0) * CO);
+        const int voff = (((py + 2 * RW * half) * w + 2 * j) * CO + 4 * g) * SZ;
+        const int rstep = 2 * w * CO * SZ;
 #pragma unroll
         for (int m = 0; m < RW; ++m)
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const int y = y0 + py + 2 * (RW * half + m), x = x0 + 2 * j + p;
-                if (y < h && x < w) {
-                    const size_t pi = ((size_t)n * h + y) * w + x;
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const int co = f * 16 + 4 * g;
-                        if (co < CO) {
-                            float v4[4] = {acc[m][p][f][0], acc[m][p][f][1], acc[m][p][f][2], acc[m][p][f][3]};
-                            store4<T, CO>(out + pi * CO + co, co, v4);
-                        }
-                    }
-                }
-            }
+                for (int f = 0; f < NF; ++f)
+                    buf_store4<T>(orc, voff, m * rstep + (p * CO + f * 16) * SZ, acc[m][p][f]);
     }
 }
 

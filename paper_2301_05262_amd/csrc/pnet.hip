@@ -66,7 +66,8 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
 
     load_halo_tile<D, IN_F32, CS, CU, CST, TH, SUM>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform in the wave: keep it in a scalar register
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int px = lane & 15, g = lane >> 4;
     const u32x4* wpk = reinterpret_cast<const u32x4*>(a.wpk);
     f32x4 acc[MF][NF];

@@ -29,6 +29,7 @@ namespace {
 constexpr uint32_t kEmptyDepth = 0x7F800000u;
 constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr int kScanThreads = 1024;
+constexpr int kGroup = 32;            // virtual triangles per group of the item -> triangle search
 constexpr int kRasterBlocks = 2048;   // 8192 waves: 32 per CU on 256 CUs, one resident round
 
 __device__ __forceinline__ void to_clip(const Mat4& M, float x, float y, float z, float c[4]) {
@@ -224,7 +225,9 @@ __global__ void __launch_bounds__(256) k_tri_setup(const float* __restrict__ tri
 // (base[b] = sum of totals of blocks < b, base[nblk] = all tiles); one block,
 // coalesced loads, wave-level scans.
 __global__ void __launch_bounds__(kScanThreads) k_block_scan(const int* __restrict__ block_sum, int nblk,
-                                                             long long* __restrict__ base) {
+                                                             long long* __restrict__ base,
+                                                             const int* __restrict__ local_off, int nv,
+                                                             long long* __restrict__ gbase) {
     __shared__ long long wsum[kScanThreads / 64];
     __shared__ long long carry;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -248,38 +251,89 @@ __global__ void __launch_bounds__(kScanThreads) k_block_scan(const int* __restri
         __syncthreads();
     }
     if (tid == 0) base[nblk] = carry;
+    __syncthreads();
+    // first item of every group of kGroup consecutive virtual triangles
+    const int ngroups = (nv + kGroup - 1) / kGroup;
+    for (int g = tid; g <= ngroups; g += kScanThreads) {
+        const int t = g * kGroup;
+        gbase[g] = (t < nv) ? base[t >> 8] + local_off[t] : carry;
+    }
 }
-
-// First tile item of triangle t (t == n gives the total).
-__device__ __forceinline__ long long tri_start(const long long* __restrict__ base,
-                                               const int* __restrict__ local_off, int t, int n) {
-    return (t >= n) ? base[(n + 255) >> 8] : base[t >> 8] + local_off[t];
-}
-
 
 // The virtual triangle holding tile item `item` (the largest v with
-// start(v) <= item) and the item's index within that triangle.  Two short
-// binary searches: over the block bases, then over the block's local offsets.
-__device__ __forceinline__ int find_tri(const long long* __restrict__ base,
-                                       const int* __restrict__ local_off, int nv, long long item,
-                                       int* local) {
-    const int nblk = (nv + 255) >> 8;
-    int lo = 0, hi = nblk;
+// start(v) <= item) and the item's index within that triangle.  A binary
+// search over the group starts (a few KB, cache resident) finds the group of
+// kGroup triangles; one batch of vector loads brings the group's local
+// offsets, and a branch-free pass over them finds the triangle.
+__device__ __forceinline__ int find_tri(const long long* __restrict__ gbase, const int* __restrict__ local_off,
+                                       int nv, long long item, int* local) {
+    const int ngroups = (nv + kGroup - 1) / kGroup;
+    int lo = 0, hi = ngroups;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (base[mid] <= item) lo = mid; else hi = mid;
+        if (gbase[mid] <= item) lo = mid; else hi = mid;
     }
-    const int rel = (int)(item - base[lo]);
-    int a = lo << 8, e = min(nv, a + 256);
-    while (e - a > 1) {
-        const int mid = (a + e) >> 1;
-        if (local_off[mid] <= rel) a = mid; else e = mid;
+    const int t0 = lo * kGroup;
+    const int rel = (int)(item - gbase[lo]);
+    const int e = min(kGroup, nv - t0);
+    const int4* q = reinterpret_cast<const int4*>(local_off + t0);
+    int off[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup / 4; ++u) {
+        const int4 v = q[u];
+        off[4 * u] = v.x; off[4 * u + 1] = v.y; off[4 * u + 2] = v.z; off[4 * u + 3] = v.w;
     }
-    *local = rel - local_off[a];
-    return a;
+    // offsets are non-decreasing within the group (a block-local scan), so
+    // the entries <= rel form a prefix; entries past the group end are ignored
+    int cnt = 0, best = 0;
+#pragma unroll
+    for (int i = 1; i < kGroup; ++i) {
+        const int d = off[i] - off[0];
+        const bool le = (i < e) & (d <= rel);
+        cnt += le ? 1 : 0;
+        best = le ? d : best;
+    }
+    *local = rel - best;
+    return t0 + cnt;
 }
 
 __device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// One (triangle, 8x8 tile) item, one texel per lane.
+__device__ __forceinline__ void raster_item(const TriCoef& c, int vk, int tx, int ty, int lx, int ly, int n_tris,
+                                            int w0, int h0, int w1, int h1, bool k0, bool k1, void* o0,
+                                            void* o1) {
+    const bool pass = vk >= n_tris;
+    const int t = vk - (pass ? n_tris : 0);
+    const int rw = pass ? w1 : w0, rh = pass ? h1 : h0;
+    const int i = tx * 8 + lx, j = ty * 8 + ly;
+    if (i >= rw || j >= rh) return;
+    const double px = (double)(256 * i + 128), py = (double)(256 * j + 128);
+    const double e0 = fma(c.dx[0], py, fma(-c.dy[0], px, c.c[0]));
+    const double e1 = fma(c.dx[1], py, fma(-c.dy[1], px, c.c[1]));
+    const double e2 = fma(c.dx[2], py, fma(-c.dy[2], px, c.c[2]));
+    const int incl = c.incl;
+    const bool in0 = (e0 > 0.0) | ((e0 == 0.0) & ((incl & 1) != 0));
+    const bool in1 = (e1 > 0.0) | ((e1 == 0.0) & ((incl & 2) != 0));
+    const bool in2 = (e2 > 0.0) | ((e2 == 0.0) & ((incl & 4) != 0));
+    if (!(in0 & in1 & in2)) return;
+    double num = e0 * c.z[0];
+    num = num + e1 * c.z[1];
+    num = num + e2 * c.z[2];
+    const double q0 = num * c.inv_area;
+    const double q = fma(fma(-q0, c.area, num), c.inv_area, q0);
+    const float d = (float)q;
+    if (!(d >= 0.0f && d <= 1.0f)) return;
+    uint32_t bits = __float_as_uint(d);
+    if ((bits & 0x7FFFFFFFu) == 0) bits = 0;  // -0 -> +0
+    const size_t o = (size_t)j * (size_t)rw + (size_t)i;
+    if (pass ? k1 : k0) {
+        const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
+        atomicMin(reinterpret_cast<unsigned long long*>(pass ? o1 : o0) + o, key);
+    } else {
+        atomicMin(reinterpret_cast<uint32_t*>(pass ? o1 : o0) + o, bits);
+    }
+}
 
 // Each wave takes chunks of 64 consecutive tile items.  Lane k first finds
 // the triangle and tile of item k of the chunk (64 searches in flight at
@@ -297,12 +351,12 @@ __device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_
 // and the first quotient is within one ulp), so it equals the IEEE division.
 __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ setup,
                                                 const TriCoef* __restrict__ coef,
-                                                const long long* __restrict__ base,
+                                                const long long* __restrict__ gbase,
                                                 const int* __restrict__ local_off, int n_tris,
                                                 RasterPasses P) {
     const int lane = threadIdx.x & 63;
     const int nv = P.npass * n_tris;             // virtual triangles
-    const long long total = tri_start(base, local_off, nv, nv);
+    const long long total = gbase[(nv + kGroup - 1) / kGroup];
     const long long nchunks = (total + 63) >> 6;
     const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
     const int w0 = P.p[0].w, h0 = P.p[0].h, w1 = P.p[1].w, h1 = P.p[1].h;
@@ -316,7 +370,7 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
         int v = 0, tx = 0, ty = 0;
         if (item < total) {
             int local;
-            v = find_tri(base, local_off, nv, item, &local);
+            v = find_tri(gbase, local_off, nv, item, &local);
             const int ntx = setup[v].ntx;
             tx = setup[v].tx0 + local % ntx;
             ty = setup[v].ty0 + local / ntx;
@@ -324,38 +378,7 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
         const int cnt = (int)min((long long)64, total - (chunk << 6));
         for (int k = 0; k < cnt; ++k) {
             const int vk = bcast(v, k);
-            const bool pass = vk >= n_tris;
-            const int t = vk - (pass ? n_tris : 0);
-            const int rw = pass ? w1 : w0, rh = pass ? h1 : h0;
-            const int i = bcast(tx, k) * 8 + lx;
-            const int j = bcast(ty, k) * 8 + ly;
-            if (i >= rw || j >= rh) continue;
-            const TriCoef& c = coef[vk];
-            const double px = (double)(256 * i + 128), py = (double)(256 * j + 128);
-            const double e0 = fma(c.dx[0], py, fma(-c.dy[0], px, c.c[0]));
-            const double e1 = fma(c.dx[1], py, fma(-c.dy[1], px, c.c[1]));
-            const double e2 = fma(c.dx[2], py, fma(-c.dy[2], px, c.c[2]));
-            const int incl = c.incl;
-            const bool in0 = (e0 > 0.0) | ((e0 == 0.0) & ((incl & 1) != 0));
-            const bool in1 = (e1 > 0.0) | ((e1 == 0.0) & ((incl & 2) != 0));
-            const bool in2 = (e2 > 0.0) | ((e2 == 0.0) & ((incl & 4) != 0));
-            if (!(in0 & in1 & in2)) continue;
-            double num = e0 * c.z[0];
-            num = num + e1 * c.z[1];
-            num = num + e2 * c.z[2];
-            const double q0 = num * c.inv_area;
-            const double q = fma(fma(-q0, c.area, num), c.inv_area, q0);
-            const float d = (float)q;
-            if (!(d >= 0.0f && d <= 1.0f)) continue;
-            uint32_t bits = __float_as_uint(d);
-            if ((bits & 0x7FFFFFFFu) == 0) bits = 0;  // -0 -> +0
-            const size_t o = (size_t)j * (size_t)rw + (size_t)i;
-            if (pass ? k1 : k0) {
-                const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
-                atomicMin(reinterpret_cast<unsigned long long*>(pass ? o1 : o0) + o, key);
-            } else {
-                atomicMin(reinterpret_cast<uint32_t*>(pass ? o1 : o0) + o, bits);
-            }
+            raster_item(coef[vk], vk, bcast(tx, k), bcast(ty, k), lx, ly, n_tris, w0, h0, w1, h1, k0, k1, o0, o1);
         }
     }
 }
@@ -367,6 +390,14 @@ __device__ __forceinline__ float lin_depth(float q, float nl, float fl) {
 }
 
 // FS: 0 = HARD6, 1 = SOFT8, 2 = PAPER4
+//
+// Each thread carries kGatherPx pixels of one row (stride 256) through the
+// three dependent fetches -- camera key, then the key's triangle, then the
+// shadow-map texel -- one stage at a time, so a wave has that many
+// independent fetches in flight at each stage instead of one.  The
+// arithmetic of every pixel is unchanged.
+constexpr int kGatherPx = 4;
+
 template <int FS>
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                                                 const float* __restrict__ normals, int n_tris,
@@ -376,128 +407,163 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                                                 float* __restrict__ feat, uint8_t* __restrict__ mask) {
     constexpr bool SOFT = FS == 1;
     constexpr int C = FS == 1 ? 8 : (FS == 2 ? 4 : 6);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int PX = kGatherPx;
     const int j = blockIdx.y;
-    if (i >= w) return;
-    const size_t p = (size_t)j * (size_t)w + (size_t)i;
-    float f[C];
+    const int ib = blockIdx.x * (256 * PX) + threadIdx.x;
+    // stage 1: camera keys
+    unsigned long long key[PX];
 #pragma unroll
-    for (int c = 0; c < C; ++c) f[c] = 0.0f;
-    uint8_t mk = 0;
-    const unsigned long long key = gbuf[p];
-    const uint32_t t = (uint32_t)(key & 0xFFFFFFFFull);
-    bool fg = key != kEmptyKey && (int)t < n_tris;
-    double D[3], tt = 0.0;
-    if (fg) {
+    for (int k = 0; k < PX; ++k) {
+        const int i = ib + 256 * k;
+        key[k] = (i < w) ? gbuf[(size_t)j * (size_t)w + (size_t)i] : kEmptyKey;
+    }
+    // stage 2: the keys' triangles (vertex 0 and the face normal)
+    float V0[PX][3], N[PX][3];
+    bool fg[PX];
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+        const uint32_t t = (uint32_t)(key[k] & 0xFFFFFFFFull);
+        fg[k] = key[k] != kEmptyKey && (int)t < n_tris;
+        const size_t tc = fg[k] ? t : 0;          // triangle 0 stands in for background pixels
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            V0[k][d] = n_tris > 0 ? tris[9 * tc + d] : 0.0f;
+            N[k][d] = n_tris > 0 ? normals[3 * tc + d] : 0.0f;
+        }
+    }
+    // stage 3: receiver, light-view projection, texel address
+    double D[PX][3], tt[PX];
+    float Pw[PX][3], c3[PX][4];
+    bool inside[PX];
+    float zf[PX];
+    int ti[PX], tj[PX];
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+        const int i = ib + 256 * k;
+        tt[k] = 0.0;
         // receiver: the pixel-centre camera ray meets the triangle's plane (float64)
         const double ndcx = (2.0 * ((double)i + 0.5)) / (double)w - 1.0;
         const double ndcy = (2.0 * ((double)j + 0.5)) / (double)h - 1.0;
         const double ax = ndcx * (double)P.tanx, ay = ndcy * (double)P.tany;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) D[k] = ((double)P.fwd[k] + ax * (double)P.right[k]) + ay * (double)P.up[k];
-        const float* V0 = tris + 9 * (size_t)t;
-        const float* N = normals + 3 * (size_t)t;
-        double num = (double)N[0] * ((double)V0[0] - (double)P.E[0]);
-        num = num + (double)N[1] * ((double)V0[1] - (double)P.E[1]);
-        num = num + (double)N[2] * ((double)V0[2] - (double)P.E[2]);
-        double den = (double)N[0] * D[0];
-        den = den + (double)N[1] * D[1];
-        den = den + (double)N[2] * D[2];
-        if (den == 0.0) fg = false;
-        else tt = num / den;
-    }
-    if (fg) {
-        const float* N = normals + 3 * (size_t)t;
-        float Pw[3];
+        for (int d = 0; d < 3; ++d) D[k][d] = ((double)P.fwd[d] + ax * (double)P.right[d]) + ay * (double)P.up[d];
+        double num = (double)N[k][0] * ((double)V0[k][0] - (double)P.E[0]);
+        num = num + (double)N[k][1] * ((double)V0[k][1] - (double)P.E[1]);
+        num = num + (double)N[k][2] * ((double)V0[k][2] - (double)P.E[2]);
+        double den = (double)N[k][0] * D[k][0];
+        den = den + (double)N[k][1] * D[k][1];
+        den = den + (double)N[k][2] * D[k][2];
+        if (den == 0.0) fg[k] = false;
+        else tt[k] = num / den;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Pw[k] = (float)((double)P.E[k] + tt * D[k]);
-        float n0 = N[0], n1 = N[1], n2 = N[2];
-        const float vx = P.E[0] - Pw[0], vy = P.E[1] - Pw[1], vz = P.E[2] - Pw[2];
-        float sgn = n0 * vx + n1 * vy;
-        sgn = sgn + n2 * vz;
-        if (sgn < 0.0f) { n0 = -n0; n1 = -n1; n2 = -n2; }
-        float dv = (Pw[0] - P.E[0]) * P.fwd[0] + (Pw[1] - P.E[1]) * P.fwd[1];
-        dv = dv + (Pw[2] - P.E[2]) * P.fwd[2];
-        float c[4];
-        to_clip(P.ml, Pw[0], Pw[1], Pw[2], c);
-        bool inside = c[3] > 1e-6f;
-        float zf = P.fl, z = P.fl;
-        int ti = 0, tj = 0;
-        if (inside) {
-            const float nx = c[0] / c[3], ny = c[1] / c[3], nz = c[2] / c[3];
+        for (int d = 0; d < 3; ++d) Pw[k][d] = (float)((double)P.E[d] + tt[k] * D[k][d]);
+        to_clip(P.ml, Pw[k][0], Pw[k][1], Pw[k][2], c3[k]);
+        inside[k] = fg[k] && c3[k][3] > 1e-6f;
+        zf[k] = P.fl;
+        ti[k] = 0;
+        tj[k] = 0;
+        if (inside[k]) {
+            const float nx = c3[k][0] / c3[k][3], ny = c3[k][1] / c3[k][3], nz = c3[k][2] / c3[k][3];
             const float sx = (nx * 0.5f + 0.5f) * (float)P.S;
             const float sy = (ny * 0.5f + 0.5f) * (float)P.S;
-            zf = lin_depth(nz, P.nl, P.fl);
-            inside = sx >= 0.0f && sx < (float)P.S && sy >= 0.0f && sy < (float)P.S && nz >= 0.0f &&
-                     nz <= 1.0f;
-            if (inside) {
-                ti = (int)floorf(sx);
-                tj = (int)floorf(sy);
-                const uint32_t b = sm[(size_t)tj * (size_t)P.S + (size_t)ti];
-                if (b == kEmptyDepth) inside = false;
-                else z = lin_depth(__uint_as_float(b), P.nl, P.fl);
+            zf[k] = lin_depth(nz, P.nl, P.fl);
+            inside[k] = sx >= 0.0f && sx < (float)P.S && sy >= 0.0f && sy < (float)P.S && nz >= 0.0f &&
+                        nz <= 1.0f;
+            if (inside[k]) {
+                ti[k] = (int)floorf(sx);
+                tj[k] = (int)floorf(sy);
             }
-        }
-        // slope-scaled depth bias from the angle between normal and light direction
-        const float tau = (2.0f * P.tanl) / (float)P.S;
-        const float lx = P.L[0] - Pw[0], ly = P.L[1] - Pw[1], lz = P.L[2] - Pw[2];
-        float ll = lx * lx + ly * ly;
-        ll = ll + lz * lz;
-        const float len = sqrtf(ll);
-        const float hx = lx / len, hy = ly / len, hz = lz / len;
-        float cl = n0 * hx + n1 * hy;
-        cl = cl + n2 * hz;
-        const float sn = sqrtf(fmaxf(1.0f - cl * cl, 0.0f));
-        const float tq = sn / fmaxf(cl, 1e-3f);
-        const float beta = (zf * tau) * (1.0f + 1.5f * fminf(tq, 10.0f));
-        mk = (inside && zf > z + beta) ? 1 : 0;
-        if constexpr (FS == 2) {
-            // c_e with the emitter-size offset, z/z_f, z - z_f, c_c/d
-            float vv = vx * vx + vy * vy;
-            vv = vv + vz * vz;
-            float cc = n0 * vx + n1 * vy;
-            cc = cc + n2 * vz;
-            cc = cc / sqrtf(vv);
-            f[0] = cl + P.r_e / 0.0625f;
-            f[1] = z / zf;
-            f[2] = (z - zf) / P.fl;
-            f[3] = cc / dv;
-        } else {
-            f[0] = dv / P.fc;
-            f[1] = n0;
-            f[2] = n1;
-            f[3] = n2;
-            f[4] = (z - zf) / P.fl;
-            f[5] = z / P.fl;
-        }
-        if constexpr (SOFT) {
-            float zb = zf;
-            if (inside) {
-                const float thr = zf - beta;
-                float sum = 0.0f;
-                int cnt = 0;
-                for (int dj = -3; dj <= 3; ++dj) {
-                    const int jj = tj + dj;
-                    if (jj < 0 || jj >= P.S) continue;
-                    for (int di = -3; di <= 3; ++di) {
-                        const int ii = ti + di;
-                        if (ii < 0 || ii >= P.S) continue;
-                        const uint32_t b = sm[(size_t)jj * (size_t)P.S + (size_t)ii];
-                        if (b == kEmptyDepth) continue;
-                        const float q = lin_depth(__uint_as_float(b), P.nl, P.fl);
-                        if (q < thr) { sum = sum + q; ++cnt; }
-                    }
-                }
-                if (cnt > 0) zb = sum / (float)cnt;
-            }
-            f[C - 2] = P.r_e / 0.2f;
-            f[C - 1] = zb / P.fl;
         }
     }
-    float* o = feat + p * C;
+    // stage 4: shadow-map texels
+    uint32_t tex[PX];
 #pragma unroll
-    for (int c = 0; c < C; ++c) o[c] = f[c];
-    if (mask) mask[p] = mk;
+    for (int k = 0; k < PX; ++k) tex[k] = sm[(size_t)tj[k] * (size_t)P.S + (size_t)ti[k]];
+    // stage 5: features and mask
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+        const int i = ib + 256 * k;
+        if (i >= w) continue;
+        const size_t p = (size_t)j * (size_t)w + (size_t)i;
+        float f[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = 0.0f;
+        uint8_t mk = 0;
+        if (fg[k]) {
+            float n0 = N[k][0], n1 = N[k][1], n2 = N[k][2];
+            const float vx = P.E[0] - Pw[k][0], vy = P.E[1] - Pw[k][1], vz = P.E[2] - Pw[k][2];
+            float sgn = n0 * vx + n1 * vy;
+            sgn = sgn + n2 * vz;
+            if (sgn < 0.0f) { n0 = -n0; n1 = -n1; n2 = -n2; }
+            float dv = (Pw[k][0] - P.E[0]) * P.fwd[0] + (Pw[k][1] - P.E[1]) * P.fwd[1];
+            dv = dv + (Pw[k][2] - P.E[2]) * P.fwd[2];
+            bool ins = inside[k];
+            float z = P.fl;
+            if (ins) {
+                if (tex[k] == kEmptyDepth) ins = false;
+                else z = lin_depth(__uint_as_float(tex[k]), P.nl, P.fl);
+            }
+            // slope-scaled depth bias from the angle between normal and light direction
+            const float tau = (2.0f * P.tanl) / (float)P.S;
+            const float lx = P.L[0] - Pw[k][0], ly = P.L[1] - Pw[k][1], lz = P.L[2] - Pw[k][2];
+            float ll = lx * lx + ly * ly;
+            ll = ll + lz * lz;
+            const float len = sqrtf(ll);
+            const float hx = lx / len, hy = ly / len, hz = lz / len;
+            float cl = n0 * hx + n1 * hy;
+            cl = cl + n2 * hz;
+            const float sn = sqrtf(fmaxf(1.0f - cl * cl, 0.0f));
+            const float tq = sn / fmaxf(cl, 1e-3f);
+            const float beta = (zf[k] * tau) * (1.0f + 1.5f * fminf(tq, 10.0f));
+            mk = (ins && zf[k] > z + beta) ? 1 : 0;
+            if constexpr (FS == 2) {
+                // c_e with the emitter-size offset, z/z_f, z - z_f, c_c/d
+                float vv = vx * vx + vy * vy;
+                vv = vv + vz * vz;
+                float cc = n0 * vx + n1 * vy;
+                cc = cc + n2 * vz;
+                cc = cc / sqrtf(vv);
+                f[0] = cl + P.r_e / 0.0625f;
+                f[1] = z / zf[k];
+                f[2] = (z - zf[k]) / P.fl;
+                f[3] = cc / dv;
+            } else {
+                f[0] = dv / P.fc;
+                f[1] = n0;
+                f[2] = n1;
+                f[3] = n2;
+                f[4] = (z - zf[k]) / P.fl;
+                f[5] = z / P.fl;
+            }
+            if constexpr (SOFT) {
+                float zb = zf[k];
+                if (ins) {
+                    const float thr = zf[k] - beta;
+                    float sum = 0.0f;
+                    int cnt = 0;
+                    for (int dj = -3; dj <= 3; ++dj) {
+                        const int jj = tj[k] + dj;
+                        if (jj < 0 || jj >= P.S) continue;
+                        for (int di = -3; di <= 3; ++di) {
+                            const int ii = ti[k] + di;
+                            if (ii < 0 || ii >= P.S) continue;
+                            const uint32_t b = sm[(size_t)jj * (size_t)P.S + (size_t)ii];
+                            if (b == kEmptyDepth) continue;
+                            const float q = lin_depth(__uint_as_float(b), P.nl, P.fl);
+                            if (q < thr) { sum = sum + q; ++cnt; }
+                        }
+                    }
+                    if (cnt > 0) zb = sum / (float)cnt;
+                }
+                f[C - 2] = P.r_e / 0.2f;
+                f[C - 1] = zb / P.fl;
+            }
+        }
+        float* o = feat + p * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[c] = f[c];
+        if (mask) mask[p] = mk;
+    }
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -505,9 +571,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 size_t raster_workspace_bytes(int n_tris) {
-    const size_t nv = 2 * (size_t)n_tris, nblk = (nv + 255) / 256;
+    const size_t nv = 2 * (size_t)n_tris, nblk = (nv + 255) / 256, ng = (nv + kGroup - 1) / kGroup;
     return align256(nv * sizeof(TriSetup)) + align256(nv * sizeof(TriCoef)) + align256(nv * 4) +
-           align256(nblk * 4) + align256((nblk + 1) * 8);
+           align256(nblk * 4) + align256((nblk + 1) * 8) + align256((ng + 1) * 8);
 }
 
 hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws, hipStream_t s) {
@@ -533,6 +599,8 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     int* block_sum = reinterpret_cast<int*>(wsb);
     wsb += align256((size_t)nblk * 4);
     long long* base = reinterpret_cast<long long*>(wsb);
+    wsb += align256(((size_t)nblk + 1) * 8);
+    long long* gbase = reinterpret_cast<long long*>(wsb);
     {
         TraceScope ts("setup+clear", sfx, s);
         const int fill_blocks = (int)min((size_t)1024, (most / 16 + 255) / 256 + 1);
@@ -542,11 +610,11 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     if (n_tris == 0) return hipGetLastError();
     {
         TraceScope ts("tile_scan", sfx, s);
-        k_block_scan<<<1, kScanThreads, 0, s>>>(block_sum, nblk, base);
+        k_block_scan<<<1, kScanThreads, 0, s>>>(block_sum, nblk, base, local_off, nv, gbase);
     }
     {
         TraceScope ts("raster", sfx, s);
-        k_raster<<<kRasterBlocks, 256, 0, s>>>(setup, coef, base, local_off, n_tris, P);
+        k_raster<<<kRasterBlocks, 256, 0, s>>>(setup, coef, gbase, local_off, n_tris, P);
     }
     return hipGetLastError();
 }
@@ -554,7 +622,7 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
                   const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s) {
-    dim3 grid((w + 255) / 256, h);
+    dim3 grid((w + 256 * kGatherPx - 1) / (256 * kGatherPx), h);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
     TraceScope ts("gather", fs == 1 ? " soft8" : (fs == 2 ? " paper4" : " hard6"), s);
     if (fs == 1)
