@@ -83,8 +83,8 @@ def stage_costs(widths, c_in, h, w, dtype):
     k = f"conv3x3 {w0}+{w1}->{w0} Head"
     fl, by = out[k]
     out[k] = (fl + 2.0 * L0 * w0, by)          # the fused 1x1 head
-    # decoder stages at these sizes run as one phase-form launch (interior
-    # tiles in the phase form, border bands in the general form)
+    # decoder stages at these sizes run as one launch (interior tiles in the
+    # phase form, border bands in the general form)
     for key in (f"conv3x3 {w1}+{w2}->{w1} Store", f"conv3x3 {w0}+{w1}->{w0} Head"):
         out[key + " phase"] = out[key]
     return out

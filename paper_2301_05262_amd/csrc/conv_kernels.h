@@ -199,7 +199,7 @@ __device__ __forceinline__ void copy_batched(S1 src1, D1 dst1, S2 src2, D2 dst2)
 // tiles' loads are all issued before the first store.
 // Rows longer than the block are split into NS equal pieces (virtual rows).
 template <int ROWS1, int K1, int ROWS2, int K2, class L1, class S1, class L2, class S2>
-__device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2);
+__device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2, int tid);
 
 __host__ __device__ constexpr int row_pieces(int k) {
     int ns = (k + kThreads - 1) / kThreads;
@@ -214,26 +214,26 @@ struct RowSplit {
 };
 
 template <int ROWS1, int K1, int ROWS2, int K2, class L1, class S1, class L2, class S2>
-__device__ __forceinline__ void copy_rows2_split(L1 ld1, S1 st1, L2 ld2, S2 st2) {
+__device__ __forceinline__ void copy_rows2_split(L1 ld1, S1 st1, L2 ld2, S2 st2, int tid) {
     using A = RowSplit<K1>;
     using B = RowSplit<K2>;
     auto l1 = [&](int vr, int k) { return ld1(vr / A::NS, (vr % A::NS) * A::KP + k); };
     auto s1 = [&](int vr, int k, const u32x4& v) { st1(vr / A::NS, (vr % A::NS) * A::KP + k, v); };
     auto l2 = [&](int vr, int k) { return ld2(vr / B::NS, (vr % B::NS) * B::KP + k); };
     auto s2 = [&](int vr, int k, const u32x4& v) { st2(vr / B::NS, (vr % B::NS) * B::KP + k, v); };
-    copy_rows2<ROWS1 * A::NS, A::KP, ROWS2 * B::NS, B::KP>(l1, s1, l2, s2);
+    copy_rows2<ROWS1 * A::NS, A::KP, ROWS2 * B::NS, B::KP>(l1, s1, l2, s2, tid);
 }
 
 template <int ROWS1, int K1, int ROWS2, int K2, class L1, class S1, class L2, class S2>
-__device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2) {
+__device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2, int tid) {
     if constexpr (K1 > kThreads || K2 > kThreads) {
-        copy_rows2_split<ROWS1, K1, ROWS2, K2>(ld1, st1, ld2, st2);
+        copy_rows2_split<ROWS1, K1, ROWS2, K2>(ld1, st1, ld2, st2, tid);
         return;
     } else {
     constexpr int R1 = kThreads / K1, R2 = kThreads / K2;
     constexpr int P1 = (ROWS1 + R1 - 1) / R1, P2 = (ROWS2 + R2 - 1) / R2;
-    const int k1 = threadIdx.x % K1, r1 = threadIdx.x / K1;
-    const int k2 = threadIdx.x % K2, r2 = threadIdx.x / K2;
+    const int k1 = tid % K1, r1 = tid / K1;
+    const int k2 = tid % K2, r2 = tid / K2;
     // loads are unconditional (rows clamped into the tile) so that no value
     // has to be merged across branches; only the stores are predicated
     u32x4 v1[P1], v2[P2];
@@ -250,23 +250,28 @@ __device__ __forceinline__ void copy_rows2(L1 ld1, S1 st1, L2 ld2, S2 st2) {
     }
 }
 
-// One tile only.
-template <int ROWS, int K, class L, class S>
-__device__ __forceinline__ void copy_rows1(L ld, S st) {
+// One tile only; loads and stores go in batches of at most MAXP passes (the
+// staging registers a batch needs).
+template <int ROWS, int K, int MAXP = 64, class L, class S>
+__device__ __forceinline__ void copy_rows1(L ld, S st, int tid) {
     if constexpr (K > kThreads) {
         using A = RowSplit<K>;
         auto l = [&](int vr, int k) { return ld(vr / A::NS, (vr % A::NS) * A::KP + k); };
         auto s = [&](int vr, int k, const u32x4& v) { st(vr / A::NS, (vr % A::NS) * A::KP + k, v); };
-        copy_rows1<ROWS * A::NS, A::KP>(l, s);
+        copy_rows1<ROWS * A::NS, A::KP, MAXP>(l, s, tid);
     } else {
         constexpr int R = kThreads / K, P = (ROWS + R - 1) / R;
-        const int k = threadIdx.x % K, r0 = threadIdx.x / K;
-        u32x4 v[P];
+        constexpr int PB = P < MAXP ? P : MAXP;
+        const int k = tid % K, r0 = tid / K;
 #pragma unroll
-        for (int p = 0; p < P; ++p) v[p] = ld(min(r0 + p * R, ROWS - 1), k);
+        for (int p0 = 0; p0 < P; p0 += PB) {
+            u32x4 v[PB];
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-            if (r0 < R && r0 + p * R < ROWS) st(r0 + p * R, k, v[p]);
+            for (int p = 0; p < PB; ++p) v[p] = ld(min(r0 + (p0 + p) * R, ROWS - 1), k);
+#pragma unroll
+            for (int p = 0; p < PB; ++p)
+                if (p0 + p < P && r0 < R && r0 + (p0 + p) * R < ROWS) st(r0 + (p0 + p) * R, k, v[p]);
+        }
     }
 }
 
@@ -360,11 +365,11 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
         *reinterpret_cast<u32x4*>(&lowt[(r * LT::LW + c) * LT::LCST + ch * EPB]) = v;
     };
     if constexpr (NCH_S > 0 && CU > 0)
-        copy_rows2<TH + 2, WP * NCH_S, LT::LH, LT::LW * NCH_U>(skip_ld, skip_st, low_ld, low_st);
+        copy_rows2<TH + 2, WP * NCH_S, LT::LH, LT::LW * NCH_U>(skip_ld, skip_st, low_ld, low_st, threadIdx.x);
     else if constexpr (NCH_S > 0)
-        copy_rows1<TH + 2, WP * NCH_S>(skip_ld, skip_st);
+        copy_rows1<TH + 2, WP * NCH_S>(skip_ld, skip_st, threadIdx.x);
     else if constexpr (CU > 0)
-        copy_rows1<LT::LH, LT::LW * NCH_U>(low_ld, low_st);
+        copy_rows1<LT::LH, LT::LW * NCH_U>(low_ld, low_st, threadIdx.x);
     if constexpr (CU > 0) {
         __syncthreads();
         // phase 2: upsampled channels from the staged rows
@@ -480,7 +485,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
     constexpr int WP = kTW + 2;
     constexpr int RPW = TH / 4;                 // rows per wave
     constexpr int MF = RPW * 2;                 // M-fragments per wave
-    static_assert(MODE != OutMode::Pool || RPW == 2, "pooling needs row pairs per wave");
+    static_assert(MODE != OutMode::Pool || RPW % 2 == 0, "pooling needs whole row pairs per wave");
     const int h = a.h, w = a.w;
 
     // ---------------- prologue: halo tile to LDS
@@ -498,11 +503,19 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // weight fragments are fetched PD k-groups ahead of their MFMAs
+    constexpr int PD = NF <= 2 ? 2 : 1;
+    u32x4 wbuf[PD + 1][NF];
+    auto wload = [&](int q, u32x4 (&dst)[NF]) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) dst[f] = buf_load16(wr, wl16, (f * NKG + q) * 1024);
+    };
+#pragma unroll
+    for (int q = 0; q < PD && q < NKG; ++q) wload(q, wbuf[q]);
 #pragma unroll
     for (int q = 0; q < NKG; ++q) {
-        u32x4 wf[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) wf[f] = buf_load16(wr, wl16, (f * NKG + q) * 1024);
+        if (q + PD < NKG) wload(q + PD, wbuf[(q + PD) % (PD + 1)]);
+        const u32x4 (&wf)[NF] = wbuf[q % (PD + 1)];
         int b = 4 * q + g;
         if (b >= NB) b = NB - 1;               // padding k: weights are zero there
         const int tap = b / BPT, cb = b - tap * BPT;
@@ -590,15 +603,18 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
         if constexpr (MODE == OutMode::Pool) {
             T* pooled = reinterpret_cast<T*>(a.pooled);
             const int hp = h >> 1, wp = w >> 1;
+            // row pair pr of this wave = fragments 4 pr + cf (upper row) and 4 pr + 2 + cf
+#pragma unroll
+            for (int pr = 0; pr < RPW / 2; ++pr)
 #pragma unroll
             for (int cf = 0; cf < 2; ++cf) {
-                const int yp = (y0 >> 1) + wave, xp = ((x0 + cf * 16 + px) >> 1);
+                const int yp = (y0 >> 1) + wave * (RPW / 2) + pr, xp = ((x0 + cf * 16 + px) >> 1);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     float mx[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const float v = fmaxf(acc[cf][f][e], acc[2 + cf][f][e]);
+                        const float v = fmaxf(acc[4 * pr + cf][f][e], acc[4 * pr + 2 + cf][f][e]);
                         mx[e] = fmaxf(v, __shfl_xor(v, 1));
                     }
                     const int co = f * 16 + 4 * g;

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
             const int c = k / G::BPT_U, cb = k - c * G::BPT_U;
             *reinterpret_cast<u32x4*>(&lowt[(r * UT::LC + c) * CSTU + cb * EPB]) = v;
         };
-        copy_rows2<UT::SR, KS, UT::LR, KL>(skip_ld, skip_st, low_ld, low_st);
+        copy_rows2<UT::SR, KS, UT::LR, KL>(skip_ld, skip_st, low_ld, low_st, threadIdx.x);
     }
     __syncthreads();
 

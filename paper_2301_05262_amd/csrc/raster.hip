@@ -337,8 +337,8 @@ __device__ __forceinline__ void raster_item(const TriCoef& c, int vk, int tx, in
 
 // Each wave takes chunks of 64 consecutive tile items.  Lane k first finds
 // the triangle and tile of item k of the chunk (64 searches in flight at
-// once); the wave then walks the chunk's items, one lane per texel of the 8x8
-// tile, with the item's triangle coefficients in scalar registers.  Inside
+// once) and stages that triangle's coefficient record in LDS; the wave then
+// walks the chunk's items, one lane per texel of the 8x8 tile.  Inside
 // the walk nothing waits on vector memory: the depth update is a
 // fire-and-forget integer atomicMin.
 //
@@ -364,6 +364,8 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
     void* const o0 = P.p[0].out;
     void* const o1 = P.p[1].out;
     const int lx = lane & 7, ly = lane >> 3;
+    __shared__ TriCoef lcoef[4][64];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (long long chunk = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); chunk < nchunks;
          chunk += nwaves) {
         const long long item = (chunk << 6) + lane;
@@ -376,10 +378,26 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
             ty = setup[v].ty0 + local / ntx;
         }
         const int cnt = (int)min((long long)64, total - (chunk << 6));
+        // lane k stages its item's coefficient record in the wave's LDS slots
+        // (64 vector loads in flight at once); the walk then reads each record
+        // with same-address (broadcast) LDS reads instead of scalar loads
+        {
+            const uint4* src = reinterpret_cast<const uint4*>(coef + v);
+            uint4* dst = reinterpret_cast<uint4*>(&lcoef[wv][lane]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dst[u] = src[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int k = 0; k < cnt; ++k) {
             const int vk = bcast(v, k);
-            raster_item(coef[vk], vk, bcast(tx, k), bcast(ty, k), lx, ly, n_tris, w0, h0, w1, h1, k0, k1, o0, o1);
+            raster_item(lcoef[wv][k], vk, bcast(tx, k), bcast(ty, k), lx, ly, n_tris, w0, h0, w1, h1, k0, k1, o0, o1);
         }
+        // the slots are rewritten for the next chunk only after every lane is done reading
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -393,10 +411,11 @@ __device__ __forceinline__ float lin_depth(float q, float nl, float fl) {
 //
 // Each thread carries kGatherPx pixels of one row (stride 256) through the
 // three dependent fetches -- camera key, then the key's triangle, then the
-// shadow-map texel -- one stage at a time, so a wave has that many
-// independent fetches in flight at each stage instead of one.  The
-// arithmetic of every pixel is unchanged.
-constexpr int kGatherPx = 4;
+// shadow-map texel -- one stage at a time, all loads unconditional (triangle
+// 0 and texel 0 stand in where a pixel has none).  Measured on the 1080p
+// frame, one pixel per thread with more waves in flight beats four per
+// thread: the gather is bound by its vector ALU work as much as by latency.
+constexpr int kGatherPx = 1;
 
 template <int FS>
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,

@@ -3,6 +3,9 @@ traffic figures the benchmark reports.
 
   python -m paper_2301_05262_amd.profsum stats <run_kernel_stats.csv> [title]
       markdown table of per-kernel calls / average / total time
+  python -m paper_2301_05262_amd.profsum counters <dir> [<dir> ...]
+      per-kernel means of every counter in the --pmc runs, and per-wave
+      instruction counts
   python -m paper_2301_05262_amd.profsum traffic <fetch_dir> <write_dir> [title]
       per-kernel HBM bytes per dispatch from one FETCH_SIZE and one WRITE_SIZE
       counter run (rocprofv3 --pmc ... --output-format csv), each scaled by what
@@ -109,6 +112,32 @@ def traffic_table(fetch_dir, write_dir, title="HBM traffic"):
     return "\n".join(out)
 
 
+def counters_table(dirs, title="counters"):
+    """Per kernel: mean per dispatch of every counter found in the runs, and
+    per-wave instruction counts where SQ_WAVES was collected."""
+    vals = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                k = short_name(r["Kernel_Name"])
+                vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = [f"### {title}", ""]
+    for k, cs in sorted(vals.items(), key=lambda kv: -sum(kv[1].get("SQ_WAVES", [0]))):
+        if "pack" in k or "copy" in k.lower() or "elementwise" in k:
+            continue
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        out.append(f"**`{k}`**")
+        out.append("")
+        waves = m.get("SQ_WAVES")
+        if waves:
+            per = [f"{c[3:].lower()} {m[c] / waves:.1f}" for c in sorted(m) if c.startswith("SQ_INSTS_")]
+            out.append(f"- per wave ({waves:.0f} waves sampled): " + ", ".join(per))
+        rest = [f"{c} {m[c]:.4g}" for c in sorted(m) if not c.startswith("SQ_INSTS_") and c != "SQ_WAVES"]
+        out.append("- " + ", ".join(rest))
+        out.append("")
+    return "\n".join(out)
+
+
 def recorded_traffic(md_path):
     """Kernel -> measured HBM bytes per dispatch from a committed summary, or {}
     when the summary is missing or the library sources changed since."""
@@ -129,6 +158,8 @@ def main(argv):
         print(stats_table(argv[1], *(argv[2:3])))
     elif len(argv) >= 3 and argv[0] == "traffic":
         print(traffic_table(argv[1], argv[2], *(argv[3:4])))
+    elif len(argv) >= 2 and argv[0] == "counters":
+        print(counters_table(argv[1:]))
     else:
         print(__doc__)
         return 2
