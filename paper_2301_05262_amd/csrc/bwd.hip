@@ -90,62 +90,100 @@ __device__ __forceinline__ float up_weight(int Y, int m, int hl) {
 }
 
 // dz_low[q][c] = (sum over the hi-res pixels whose bilinear taps reach q of
-// weight * dup[.][c_off + c]) * (act_low[q][c] > 0)
+// weight * dup[.][c_off + c]) * (act_low[q][c] > 0).  One thread per low-res
+// pixel and 4 channels: 16-byte loads across channels; the at most 4 x 4
+// reaching hi-res pixels and their weights are found once per thread.
 __global__ void __launch_bounds__(256) k_up_transpose_mask(const float* __restrict__ dup, int ci_total,
                                                            int c_off, const float* __restrict__ act_low,
                                                            int C, int n, int hl, int wl,
                                                            float* __restrict__ dz_low) {
-    const size_t total = (size_t)n * hl * wl * C;
+    const int C4 = C >> 2;
+    const size_t total = (size_t)n * hl * wl * C4;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int c = (int)(idx % C);
-    const size_t q = idx / C;
+    const int c = (int)(idx % C4) * 4;
+    const size_t q = idx / C4;
     const int k = (int)(q % wl);
     const int m = (int)((q / wl) % hl);
     const int f = (int)(q / ((size_t)wl * hl));
     const int H = 2 * hl, W = 2 * wl;
-    float s = 0.0f;
-    for (int Y = max(2 * m - 1, 0); Y <= min(2 * m + 2, H - 1); ++Y) {
-        const float wy = up_weight(Y, m, hl);
-        if (wy == 0.0f) continue;
-        for (int X = max(2 * k - 1, 0); X <= min(2 * k + 2, W - 1); ++X) {
-            const float wx = up_weight(X, k, wl);
-            if (wx == 0.0f) continue;
-            s += (wy * wx) * dup[(((size_t)f * H + Y) * W + X) * ci_total + c_off + c];
+    float wy[4], wx[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int Y = 2 * m - 1 + t, X = 2 * k - 1 + t;
+        wy[t] = (Y >= 0 && Y < H) ? up_weight(Y, m, hl) : 0.0f;
+        wx[t] = (X >= 0 && X < W) ? up_weight(X, k, wl) : 0.0f;
+    }
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int ty = 0; ty < 4; ++ty) {
+        if (wy[ty] == 0.0f) continue;
+        const int Y = 2 * m - 1 + ty;
+#pragma unroll
+        for (int tx = 0; tx < 4; ++tx) {
+            if (wx[tx] == 0.0f) continue;
+            const int X = 2 * k - 1 + tx;
+            const float ww = wy[ty] * wx[tx];
+            const float4 d = *reinterpret_cast<const float4*>(dup + (((size_t)f * H + Y) * W + X) * ci_total + c_off + c);
+            s.x += ww * d.x;
+            s.y += ww * d.y;
+            s.z += ww * d.z;
+            s.w += ww * d.w;
         }
     }
-    dz_low[idx] = act_low[idx] > 0.0f ? s : 0.0f;
+    const float4 av = *reinterpret_cast<const float4*>(act_low + q * C + c);
+    float4 o;
+    o.x = av.x > 0.0f ? s.x : 0.0f;
+    o.y = av.y > 0.0f ? s.y : 0.0f;
+    o.z = av.z > 0.0f ? s.z : 0.0f;
+    o.w = av.w > 0.0f ? s.w : 0.0f;
+    *reinterpret_cast<float4*>(dz_low + q * C + c) = o;
 }
 
 // ---------------------------------------------------------------- pool^T
-// dz[p][c] = (dskip[p][c] + routed max-pool gradient) * (act[p][c] > 0)
+// One channel of the max-pool adjoint: the window's gradient goes to its
+// first maximum in (0,0), (0,1), (1,0), (1,1) order; ReLU'(0) = 0.
+__device__ __forceinline__ float pool_route(float a0, float a1, float a2, float a3, float me, float d_skip,
+                                            float d_pool, int mine) {
+    int best = 0;
+    float bv = a0;
+    if (a1 > bv) { bv = a1; best = 1; }
+    if (a2 > bv) { bv = a2; best = 2; }
+    if (a3 > bv) { bv = a3; best = 3; }
+    if (!(me > 0.0f)) return 0.0f;
+    return best == mine ? d_skip + d_pool : d_skip;
+}
+
+// dz[p][c] = (dskip[p][c] + routed max-pool gradient) * (act[p][c] > 0).
+// One thread per pixel and 4 channels (16-byte accesses).
 __global__ void __launch_bounds__(256) k_pool_transpose_mask(const float* __restrict__ dskip, int ci_total,
                                                              const float* __restrict__ dpool,
                                                              const float* __restrict__ act, int C, int n,
                                                              int h, int w, float* __restrict__ dz) {
-    const size_t total = (size_t)n * h * w * C;
+    const int C4 = C >> 2;
+    const size_t total = (size_t)n * h * w * C4;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int c = (int)(idx % C);
-    const size_t p = idx / C;
+    const int c = (int)(idx % C4) * 4;
+    const size_t p = idx / C4;
     const int x = (int)(p % w);
     const int y = (int)((p / w) % h);
     const int f = (int)(p / ((size_t)w * h));
-    const float a = act[idx];
-    float g = 0.0f;
-    if (a > 0.0f) {
-        const int y0 = y & ~1, x0 = x & ~1;
-        int best = 0;
-        float bv = act[(((size_t)f * h + y0) * w + x0) * C + c];
-        for (int k = 1; k < 4; ++k) {
-            const float v = act[(((size_t)f * h + y0 + (k >> 1)) * w + x0 + (k & 1)) * C + c];
-            if (v > bv) { bv = v; best = k; }
-        }
-        const int mine = ((y - y0) << 1) | (x - x0);
-        g = dskip[p * ci_total + c];
-        if (best == mine) g += dpool[(((size_t)f * (h >> 1) + (y >> 1)) * (w >> 1) + (x >> 1)) * C + c];
-    }
-    dz[idx] = g;
+    const int y0 = y & ~1, x0 = x & ~1;
+    const int mine = ((y - y0) << 1) | (x - x0);
+    const float* r0 = act + (((size_t)f * h + y0) * w + x0) * C + c;
+    const float* r1 = r0 + (size_t)w * C;
+    const float4 w0 = *reinterpret_cast<const float4*>(r0), w1 = *reinterpret_cast<const float4*>(r0 + C);
+    const float4 w2 = *reinterpret_cast<const float4*>(r1), w3 = *reinterpret_cast<const float4*>(r1 + C);
+    const float4 a = *reinterpret_cast<const float4*>(act + p * C + c);
+    const float4 ds = *reinterpret_cast<const float4*>(dskip + p * ci_total + c);
+    const float4 dp = *reinterpret_cast<const float4*>(dpool + (((size_t)f * (h >> 1) + (y >> 1)) * (w >> 1) + (x >> 1)) * C + c);
+    float4 o;
+    o.x = pool_route(w0.x, w1.x, w2.x, w3.x, a.x, ds.x, dp.x, mine);
+    o.y = pool_route(w0.y, w1.y, w2.y, w3.y, a.y, ds.y, dp.y, mine);
+    o.z = pool_route(w0.z, w1.z, w2.z, w3.z, a.z, ds.z, dp.z, mine);
+    o.w = pool_route(w0.w, w1.w, w2.w, w3.w, a.w, ds.w, dp.w, mine);
+    *reinterpret_cast<float4*>(dz + p * C + c) = o;
 }
 
 // ------------------------------------------------------------------ wgrad
@@ -333,7 +371,7 @@ size_t head_partial_floats(int c0, size_t npix) { return (size_t)head_grid(npix)
 
 hipError_t up_transpose_mask(int c, int ci_total, int c_off, const float* dup, const float* act_low,
                              int n, int hl, int wl, float* dz_low, hipStream_t s) {
-    const size_t total = (size_t)n * hl * wl * c;
+    const size_t total = (size_t)n * hl * wl * (c / 4);
     TraceScope ts("up_transpose_mask", "", s);
     k_up_transpose_mask<<<div_up(total, 256), 256, 0, s>>>(dup, ci_total, c_off, act_low, c, n, hl, wl,
                                                            dz_low);
@@ -342,7 +380,7 @@ hipError_t up_transpose_mask(int c, int ci_total, int c_off, const float* dup, c
 
 hipError_t pool_transpose_mask(int c, int ci_total, const float* dskip, const float* dpool,
                                const float* act, int n, int h, int w, float* dz, hipStream_t s) {
-    const size_t total = (size_t)n * h * w * c;
+    const size_t total = (size_t)n * h * w * (c / 4);
     TraceScope ts("pool_transpose_mask", "", s);
     k_pool_transpose_mask<<<div_up(total, 256), 256, 0, s>>>(dskip, ci_total, dpool, act, c, n, h, w, dz);
     return hipGetLastError();
