@@ -204,9 +204,34 @@ def training_section(S, torch, seed, steps):
             "ideal_ms_at_fp32_mfma_peak": flop / MFMA_PEAK["f32"] * 1e3}
 
 
+def _time_net(torch, nsm, net, feat, vis, steps):
+    """Average ms per forward over `steps` launches, then per-kernel us from the trace."""
+    for _ in range(10):
+        net.forward(feat, vis_out=vis)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        net.forward(feat, vis_out=vis)
+    b.record()
+    torch.cuda.synchronize()
+    nsm.nsm_trace_read()
+    nsm.nsm_trace_enable(True)
+    for _ in range(max(1, steps // 4)):
+        net.forward(feat, vis_out=vis)
+    torch.cuda.synchronize()
+    per = {}
+    for name, ms in nsm.nsm_trace_read(1 << 16):
+        per.setdefault(name, []).append(ms)
+    nsm.nsm_trace_enable(False)
+    return {"network_ms": a.elapsed_time(b) / steps,
+            "kernels_us": {k: 1e3 * float(np.mean(v)) for k, v in per.items()}}
+
+
 def paper_net_section(S, torch, seed, steps):
     """The paper's own 5-level network (3x3 + 1x1 per level, avg-pool, sum skip)
-    at 1024x2048 on PAPER4 features: network ms per form, per-kernel times."""
+    at 1024x2048 on PAPER4 features, before ("paper") and after ("s2d") its
+    first-level optimisation: network ms per form, per-kernel times."""
     import paper_2301_05262_amd as nsm
     from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet
     widths = (16, 32, 64, 128, 256)
@@ -216,41 +241,24 @@ def paper_net_section(S, torch, seed, steps):
     fb = FeatureBuilder(sc)
     buf = fb(fr, fs="paper4")
     feat = buf["feat"].unsqueeze(0)
-    rng = S.SplitMix64(seed)
-    net0 = ShadowNet(4, widths, "f32", arch="paper")
-    flat = torch.from_numpy((rng.normals(net0.n_params) * 0.1).astype(np.float32))
+    vis = torch.empty((1, 1024, 2048), dtype=torch.float32, device=feat.device)
     out = {"workload": "paper5_1024x2048", "widths": list(widths), "features": "paper4",
-           "macs_per_pixel": 16208}
-    for f in ("bf16", "f16", "f32"):
-        net = ShadowNet(4, widths, f, arch="paper")
-        net.set_weights(flat)
-        vis = torch.empty((1, 1024, 2048), dtype=torch.float32, device=feat.device)
-        for _ in range(10):
-            net.forward(feat, vis_out=vis)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record()
-        for _ in range(steps):
-            net.forward(feat, vis_out=vis)
-        b.record()
-        torch.cuda.synchronize()
-        nsm.nsm_trace_read()
-        nsm.nsm_trace_enable(True)
-        for _ in range(max(1, steps // 4)):
-            net.forward(feat, vis_out=vis)
-        torch.cuda.synchronize()
-        per = {}
-        for name, ms in nsm.nsm_trace_read(1 << 16):
-            per.setdefault(name, []).append(ms)
-        nsm.nsm_trace_enable(False)
-        out[f] = {"network_ms": a.elapsed_time(b) / steps,
-                  "kernels_us": {k: 1e3 * float(np.mean(v)) for k, v in per.items()}}
+           "macs_per_pixel": 16208, "s2d": {"macs_per_pixel": 12816}}
+    for arch, dst in (("paper", out), ("paper_s2d", out["s2d"])):
+        rng = S.SplitMix64(seed)
+        net0 = ShadowNet(4, widths, "f32", arch=arch)
+        flat = torch.from_numpy((rng.normals(net0.n_params) * 0.1).astype(np.float32))
+        for f in ("bf16", "f16", "f32"):
+            net = ShadowNet(4, widths, f, arch=arch)
+            net.set_weights(flat)
+            dst[f] = _time_net(torch, nsm, net, feat, vis, steps)
     t0 = time.perf_counter()
     for _ in range(steps):
         fb(fr, fs="paper4", out=buf)
     torch.cuda.synchronize()
     out["features_ms"] = 1e3 * (time.perf_counter() - t0) / steps
-    out["paper_context"] = "RTX 2080Ti, FP16: 17.3 ms for this network (Sec. 4.5), 28 ms FP32"
+    out["paper_context"] = ("RTX 2080Ti, FP16: 17.3 ms for this network before the first-level "
+                            "optimisation and 5.84 ms after it (Sec. 4.5), 28 ms FP32")
     return out
 
 
@@ -400,7 +408,9 @@ def main():
     if args.paper_net:
         paper_net = paper_net_section(S, torch, args.seed, steps=50)
         print(f"[bench] paper net 1024x2048: bf16 {paper_net['bf16']['network_ms']:.3f} ms, "
-              f"f16 {paper_net['f16']['network_ms']:.3f} ms, f32 {paper_net['f32']['network_ms']:.3f} ms",
+              f"f16 {paper_net['f16']['network_ms']:.3f} ms, f32 {paper_net['f32']['network_ms']:.3f} ms; "
+              f"s2d form: bf16 {paper_net['s2d']['bf16']['network_ms']:.3f} ms, "
+              f"f16 {paper_net['s2d']['f16']['network_ms']:.3f} ms, f32 {paper_net['s2d']['f32']['network_ms']:.3f} ms",
               file=sys.stderr, flush=True)
     ms = results[head]["ms_per_frame"]
     line = {

@@ -87,8 +87,21 @@ typedef struct nsm_ctx nsm_ctx;
  *   3x3 w_l -> w_l, 1x1 w_l -> w_{l-1}; level 0: 3x3 and 1x1 w_0 -> w_0,
  *   then a 1x1 output conv to one channel and a sigmoid.  Flat parameters
  *   list the convs in that order (each OHWI weights then biases).
- *   Supported: c_in = 4; widths {16, 32, 64} or {16, 32, 64, 128, 256}. */
-typedef enum { NSM_ARCH_UNET = 0, NSM_ARCH_PAPER = 1 } nsm_arch;
+ *   Supported: c_in = 4; widths {16, 32, 64} or {16, 32, 64, 128, 256}.
+ * NSM_ARCH_PAPER_S2D: the paper's network after its first-level optimisation
+ *   (Sec. 4.5): the level-0 convolutions are removed.  The input is read as
+ *   2x2 blocks, (h, w, c_in) -> (h/2, w/2, 4 c_in), channel (2 dy + dx) c_in
+ *   + c of block (i, j) being channel c of pixel (2i + dy, 2j + dx), and
+ *   feeds the level-1 encoder (3x3 4 c_in -> w_1).  Levels 1..L-1 are those
+ *   of NSM_ARCH_PAPER; the level-1 decoder's 1x1 (w_1 -> w_0) is followed by
+ *   a 1x1 output conv w_0 -> 4.  Full-resolution logit at (2i + dy, 2j + dx):
+ *   the bilinear x2 upsampling of output channel 0, plus output channel
+ *   2 dy + dx unless dy = dx = 0; then the sigmoid.  Flat parameters: the
+ *   convs of NSM_ARCH_PAPER without E0 and D0, the output conv last
+ *   ([4][w_0] then 4 biases).  h and w must be even (and multiples of
+ *   2^(L-1) as for every network).  Supported: c_in = 4; widths {16, 32, 64}
+ *   or {16, 32, 64, 128, 256}. */
+typedef enum { NSM_ARCH_UNET = 0, NSM_ARCH_PAPER = 1, NSM_ARCH_PAPER_S2D = 2 } nsm_arch;
 
 typedef struct nsm_net_desc {
     int32_t arch;       /* nsm_arch */

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "NSM_OK", 1: "NSM_E_INVALID_ARG", 2: "NSM_E_SHAPE", 3: "NSM_E
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 FEATURE_SETS = {"hard6": 0, "soft8": 1, "paper4": 2}
 FEATURE_CHANNELS = {"hard6": 6, "soft8": 8, "paper4": 4}
-ARCHS = {"unet": 0, "paper": 1}
+ARCHS = {"unet": 0, "paper": 1, "paper_s2d": 2}
 
 EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",

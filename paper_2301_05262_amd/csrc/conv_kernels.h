@@ -296,7 +296,11 @@ struct LowTile {
 // a barrier: the tile is ready when it returns.
 // With SUM the upsampled channels are added to channels [0, CU) of `in`
 // (CU == CS) instead of being appended: the skip merge by algebraic sum.
-template <Dt D, bool IN_F32, int CS, int CU, int CST, int TH, bool SUM = false>
+// With S2D, `in` is the float32 full-resolution input [n][2h][2w][CS/4] read
+// through space-to-depth: channel (2 dy + dx) CS/4 + c of pixel (y, x) is
+// channel c of input pixel (2y + dy, 2x + dx), so every block of channels is
+// one contiguous run of an input row.
+template <Dt D, bool IN_F32, int CS, int CU, int CST, int TH, bool SUM = false, bool S2D = false>
 __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename DT<D>::T* lowt,
                                                const void* in, const void* low, int n, int h, int w,
                                                int x0, int y0) {
@@ -305,23 +309,39 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     constexpr int EPB = DT<D>::EPB;
     constexpr int CSP = round_up(CS, EPB);
     static_assert(!SUM || CS == CU, "a sum skip needs equal channel counts");
+    static_assert(!S2D || (IN_F32 && CS == 16), "space-to-depth reads 4-channel float32 input");
     constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
     constexpr int NCH_S = CSP / EPB, NCH_U = CU / EPB;
     // phase 1: same-resolution channels, and the low-res source rows.
     // Buffer offsets are relative to each tile's first (halo) pixel, taken
     // at clamped coordinates; pixels outside the image then read as zero.
     constexpr int SZ_IN = IN_F32 ? 4 : (int)sizeof(T);
-    const char* sbase = reinterpret_cast<const char*>(in) + ((((long long)n * h + y0 - 1) * w + x0 - 1) * CS) * SZ_IN;
+    constexpr int SPX = S2D ? 2 * (CS / 4) * 4 : CS * SZ_IN;          // bytes per pixel step
+    const int srow = S2D ? 2 * (2 * w) * (CS / 4) * 4 : w * CS * SZ_IN;  // bytes per row step
+    const char* sbase = reinterpret_cast<const char*>(in) + ((long long)n * h + y0 - 1) * srow +
+                        (long long)(x0 - 1) * SPX;
     const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase);
-    const int srow = w * CS * SZ_IN;
     auto skip_ld = [&](int r, int k) -> u32x4 {
         const int c = k / (NCH_S > 0 ? NCH_S : 1), ch = k - c * NCH_S;
         const int y = y0 + r - 1, x = x0 + c - 1;
         const bool ok = y >= 0 && y < h && x >= 0 && x < w;
         const int yr = min(max(y, 0), h - 1) - (y0 - 1), xr = min(max(x, 0), w - 1) - (x0 - 1);
-        const int voff = yr * srow + xr * (CS * SZ_IN);
+        const int voff = yr * srow + xr * SPX;
         u32x4 v;
-        if constexpr (IN_F32) {
+        if constexpr (S2D) {
+            // channels [ch EPB, ch EPB + EPB): input row 2y + (ch EPB) / 8, floats
+            // (ch EPB) % 8 .. of the two pixels 2x, 2x + 1
+            const int off = voff + ((ch * EPB) >> 3) * (srow >> 1) + ((ch * EPB) & 7) * 4;
+            float f[EPB];
+#pragma unroll
+            for (int q = 0; q < EPB / 4; ++q) {
+                // copied as bytes: a bit_cast of a vector element here read element 0
+                // for every e
+                const u32x4 u = buf_load16(sr, off + 16 * q, 0);
+                __builtin_memcpy(&f[4 * q], &u, 16);
+            }
+            v = pack_block<D>(f);
+        } else if constexpr (IN_F32) {
             // float32 features: EPB channels of block ch, zero past CS
             float f[EPB];
 #pragma unroll

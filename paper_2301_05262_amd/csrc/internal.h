@@ -104,17 +104,21 @@ hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs
 bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32);
 
 // ---------------------------------------------- the paper's network (P-net)
-enum class PMode { Store = 0, PoolOnly = 1, PoolSkip = 2, Head = 3 };
+// D2S: the stage ends in the output 1x1 conv to four channels, stored as
+// float32 [n][h][w][4] for the depth-to-space head (d2s_forward).
+enum class PMode { Store = 0, PoolOnly = 1, PoolSkip = 2, Head = 3, D2S = 4 };
 
 // One P-net stage: 3x3 conv (cs [+ cu] -> c1) + ReLU, 1x1 (c1 -> c2) + ReLU.
 // Input: `in` ([.., cs]) and/or up(low) ([.., cu] at half resolution), summed
 // when `sum` (cs == cu), concatenated otherwise (cs = 0: upsampled input only).
+// s2d: `in` is the float32 full-resolution input read through space-to-depth.
 struct PStage {
     int cs, cu;
     bool sum;
     int c1, c2;
     PMode mode;
     bool in_f32;
+    bool s2d = false;
 };
 
 struct PConvArgs {
@@ -126,7 +130,7 @@ struct PConvArgs {
     const float* b2;      // [c2]
     void* out;            // [n][h][w][c2] (Store, PoolSkip)
     void* pooled;         // [n][h/2][w/2][c2] average-pooled (PoolOnly, PoolSkip)
-    const float* head_w;  // [c2] + bias (Head)
+    const float* head_w;  // [c2] + bias (Head); [4][c2] + 4 biases (D2S)
     float* vis;
     float* logits;
     int n, h, w;
@@ -138,6 +142,9 @@ size_t pconv_w1_offset(const PStage& st, Dt dt);
 hipError_t pconv_pack(const PStage& st, Dt dt, const float* w3, const float* w1, void* packed,
                       hipStream_t s);
 hipError_t pconv_forward(const PStage& st, Dt dt, const PConvArgs& a, hipStream_t s);
+// Depth-to-space head: y4 float32 [n][h][w][4] -> vis (and logits when non-null)
+// float32 [n][2h][2w].
+hipError_t d2s_forward(const float* y4, int n, int h, int w, float* vis, float* logits, hipStream_t s);
 
 // ------------------------------------------------------ backward (float32)
 bool backward_supported(const ConvStage& st);

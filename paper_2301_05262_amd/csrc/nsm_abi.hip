@@ -151,14 +151,19 @@ nsm_status nsm_create(const nsm_net_desc* desc, nsm_dtype dtype, nsm_ctx** out) 
     if (desc->arch == NSM_ARCH_UNET && L > 4) return NSM_E_UNSUPPORTED;
     for (int l = 0; l < L; ++l)
         if (desc->widths[l] < 1) return NSM_E_UNSUPPORTED;
-    if (desc->arch != NSM_ARCH_UNET && desc->arch != NSM_ARCH_PAPER) return NSM_E_INVALID_ARG;
+    if (desc->arch != NSM_ARCH_UNET && desc->arch != NSM_ARCH_PAPER && desc->arch != NSM_ARCH_PAPER_S2D)
+        return NSM_E_INVALID_ARG;
     nsm_ctx* c = new (std::nothrow) nsm_ctx();
     if (!c) return NSM_E_DEVICE;
     c->desc = *desc;
     c->dt = static_cast<Dt>(dtype);
     const int* wd = desc->widths;
     size_t off = 0;
-    if (desc->arch == NSM_ARCH_PAPER) {
+    if (desc->arch == NSM_ARCH_PAPER || desc->arch == NSM_ARCH_PAPER_S2D) {
+        // the space-to-depth form has no level-0 convolutions: its first encoder
+        // stage reads the input rearranged to 2x2 blocks at level 1, and its
+        // last decoder stage ends in the four-channel output conv
+        const bool s2d = desc->arch == NSM_ARCH_PAPER_S2D;
         if (L != 3 && L != 5) {
             delete c;
             return NSM_E_UNSUPPORTED;
@@ -180,15 +185,19 @@ nsm_status nsm_create(const nsm_net_desc* desc, nsm_dtype dtype, nsm_ctx** out) 
         };
         static const char* pe[] = {"E0", "E1", "E2", "E3"};
         static const char* pd[] = {"D0", "D1", "D2", "D3"};
-        for (int l = 0; l < L - 1; ++l)
-            addp(pe[l], PStage{l == 0 ? desc->c_in : wd[l - 1], 0, false, wd[l], wd[l],
-                               l == 0 ? PMode::PoolOnly : PMode::PoolSkip, l == 0}, l);
+        for (int l = s2d ? 1 : 0; l < L - 1; ++l) {
+            const bool s2d_in = s2d && l == 1;
+            addp(pe[l], PStage{l == 0 ? desc->c_in : (s2d_in ? 4 * desc->c_in : wd[l - 1]), 0, false, wd[l],
+                               wd[l], l == 0 ? PMode::PoolOnly : PMode::PoolSkip, l == 0 || s2d_in, s2d_in},
+                 l);
+        }
         addp("B", PStage{wd[L - 2], 0, false, wd[L - 1], wd[L - 2], PMode::Store, false}, L - 1);
         for (int l = L - 2; l >= 1; --l)
-            addp(pd[l], PStage{wd[l], wd[l], true, wd[l], wd[l - 1], PMode::Store, false}, l);
-        addp("D0", PStage{0, wd[0], false, wd[0], wd[0], PMode::Head, false}, 0);
+            addp(pd[l], PStage{wd[l], wd[l], true, wd[l], wd[l - 1],
+                               (s2d && l == 1) ? PMode::D2S : PMode::Store, false}, l);
+        if (!s2d) addp("D0", PStage{0, wd[0], false, wd[0], wd[0], PMode::Head, false}, 0);
         c->head_w_off = off;
-        off += wd[0] + 1;
+        off += s2d ? 4 * wd[0] + 4 : wd[0] + 1;
         c->n_params = off;
         size_t pk = 0;
         for (auto& p : c->stages) {
@@ -282,7 +291,7 @@ nsm_status nsm_set_weights(nsm_ctx* ctx, const float* w, size_t n, void* stream)
     float* flat = reinterpret_cast<float*>(base + ctx->flat_off);
     if (hipMemcpyAsync(flat, w, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return NSM_E_DEVICE;
     for (const auto& p : ctx->stages) {
-        if (ctx->desc.arch == NSM_ARCH_PAPER) {
+        if (ctx->desc.arch != NSM_ARCH_UNET) {
             if (pconv_pack(p.ps, ctx->dt, flat + p.w_off, flat + p.w2_off, base + p.pk_off, s) != hipSuccess)
                 return NSM_E_LAUNCH;
             continue;
@@ -303,7 +312,7 @@ namespace {
 
 // Activation buffers of one forward pass (n frames), in the stage dtype.
 struct FwdLayout {
-    size_t skip[4], pool[4], bott, dec[4], d0act, total;
+    size_t skip[4], pool[4], bott, dec[4], d0act, head4, total;
 };
 
 size_t elem_size(Dt dt) { return dt == Dt::F32 ? 4 : 2; }
@@ -333,6 +342,8 @@ FwdLayout plan_forward(const nsm_ctx* c, int n, int h, int w, bool training) {
 
 // Paper network: skip[l] = x_l (l >= 1), pool[l] = avgpool(x_l), dec[l] = y_l
 // (decoder output at level l >= 1, w_{l-1} channels; dec[L-1] is the bottleneck).
+// Space-to-depth form: no level-0 buffers and no dec[1]; head4 holds the
+// level-1 four-channel output (float32).
 FwdLayout plan_forward_paper(const nsm_ctx* c, int n, int h, int w) {
     FwdLayout L{};
     const int lv = c->desc.levels;
@@ -345,11 +356,13 @@ FwdLayout plan_forward_paper(const nsm_ctx* c, int n, int h, int w) {
         return o;
     };
     auto px = [&](int l) { return (size_t)n * (size_t)(h >> l) * (size_t)(w >> l); };
-    for (int l = 0; l < lv - 1; ++l) {
+    const bool s2d = c->desc.arch == NSM_ARCH_PAPER_S2D;
+    for (int l = s2d ? 1 : 0; l < lv - 1; ++l) {
         if (l >= 1) L.skip[l] = take(px(l) * wd[l] * es);
         L.pool[l] = take(px(l + 1) * wd[l] * es);
     }
-    for (int l = 1; l <= lv - 1; ++l) L.dec[l] = take(px(l) * wd[l - 1] * es);
+    for (int l = s2d ? 2 : 1; l <= lv - 1; ++l) L.dec[l] = take(px(l) * wd[l - 1] * es);
+    if (s2d) L.head4 = take(px(1) * 4 * sizeof(float));
     L.total = off;
     return L;
 }
@@ -383,6 +396,16 @@ hipError_t run_forward_paper(const nsm_ctx* c, const float* feat, int n, int h, 
             a.in = ws + L.skip[l];
             a.low = ws + L.dec[l + 1];
             a.out = ws + L.dec[l];
+        } else if (p.ps.mode == PMode::D2S) {                                  // level 1 + output conv
+            a.in = ws + L.skip[l];
+            a.low = ws + L.dec[l + 1];
+            a.out = ws + L.head4;
+            a.head_w = flat + c->head_w_off;
+            hipError_t e = pconv_forward(p.ps, c->dt, a, s);
+            if (e != hipSuccess) return e;
+            e = d2s_forward(reinterpret_cast<const float*>(ws + L.head4), n, h >> 1, w >> 1, vis, logits, s);
+            if (e != hipSuccess) return e;
+            continue;
         } else {                                                               // level 0 + output
             a.low = ws + L.dec[1];
             a.head_w = flat + c->head_w_off;
@@ -555,8 +578,8 @@ nsm_status nsm_workspace_bytes(const nsm_ctx* ctx, int n, int h, int w, int trai
         *bytes = plan_training(ctx, n, h, w).total;
         return NSM_OK;
     }
-    *bytes = ctx->desc.arch == NSM_ARCH_PAPER ? plan_forward_paper(ctx, n, h, w).total
-                                              : plan_forward(ctx, n, h, w, false).total;
+    *bytes = ctx->desc.arch != NSM_ARCH_UNET ? plan_forward_paper(ctx, n, h, w).total
+                                             : plan_forward(ctx, n, h, w, false).total;
     return NSM_OK;
 }
 
@@ -566,7 +589,7 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
     nsm_status st = check_net_shape(ctx, n, h, w);
     if (st != NSM_OK) return st;
     if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
-    const bool paper = ctx->desc.arch == NSM_ARCH_PAPER;
+    const bool paper = ctx->desc.arch != NSM_ARCH_UNET;
     FwdLayout L = paper ? plan_forward_paper(ctx, n, h, w) : plan_forward(ctx, n, h, w, false);
     if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;

@@ -10,7 +10,11 @@
 // layout of v_mfma_f32_16x16x16_{bf16,f16} (K = 16 channels per MFMA), and
 // per-element for v_mfma_f32_16x16x4_f32.  Nothing of the 3x3 output
 // touches memory.  Epilogues: store; 2x2 average pool (with or without the
-// full-resolution skip store); the output 1x1 + sigmoid.
+// full-resolution skip store); the output 1x1 + sigmoid; the output 1x1 to
+// four channels of the space-to-depth form (Sec. 4.5), whose depth-to-space
+// head k_d2s_out then forms the full-resolution visibility.  The first
+// encoder stage of that form reads its input through space-to-depth in the
+// halo load, so the rearranged input never exists in memory.
 #include <hip/hip_runtime.h>
 
 #include "conv_kernels.h"
@@ -44,7 +48,7 @@ __device__ __forceinline__ f32x4 mfma_1x1(const uint2& wa, const f32x4& act, f32
     }
 }
 
-template <Dt D, bool IN_F32, int CS, int CU, bool SUM, int C1, int C2, PMode MODE, int TH>
+template <Dt D, bool IN_F32, int CS, int CU, bool SUM, int C1, int C2, PMode MODE, int TH, bool S2D>
 __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     using T = typename DT<D>::T;
     using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
@@ -64,7 +68,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
     const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
 
-    load_halo_tile<D, IN_F32, CS, CU, CST, TH, SUM>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
+    load_halo_tile<D, IN_F32, CS, CU, CST, TH, SUM, S2D>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     // the wave index is uniform in the wave: keep it in a scalar register
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -169,6 +173,39 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
                 if (a.logits) a.logits[p] = logit;
             }
         }
+    } else if constexpr (MODE == PMode::D2S) {
+        // out4[p][k] = sum_co W[k][co] y[p][co] + b[k]: per-lane partial sums over
+        // this lane's channels, summed over the four lane groups; group g stores k = g
+        float hw[4][NF2][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int f2 = 0; f2 < NF2; ++f2)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = f2 * 16 + 4 * g + e;
+                    hw[k][f2][e] = co < C2 ? a.head_w[k * C2 + co] : 0.0f;
+                }
+        const float hb = a.head_w[4 * C2 + g];
+        float* out4 = reinterpret_cast<float*>(a.out);
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
+            float s[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float t = 0.0f;
+#pragma unroll
+                for (int f2 = 0; f2 < NF2; ++f2)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) t += hw[k][f2][e] * acc2[m][f2][e];
+                t += __shfl_xor(t, 16);
+                t += __shfl_xor(t, 32);
+                s[k] = t;
+            }
+            const float mine = g == 0 ? s[0] : (g == 1 ? s[1] : (g == 2 ? s[2] : s[3]));
+            if (y < h && x < w) out4[(((size_t)n * h + y) * w + x) * 4 + g] = mine + hb;
+        }
     } else {
         if constexpr (MODE != PMode::PoolOnly) {
             T* out = reinterpret_cast<T*>(a.out);
@@ -213,6 +250,53 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     }
 }
 
+// Depth-to-space head of the space-to-depth form (Sec. 4.5).  One thread per
+// low-resolution pixel (i, j) writes the 2x2 block (2i + dy, 2j + dx):
+// logit = bilinear x2 of channel 0 (the taps of the decoder's upsampling:
+// 0.25 / 0.75 towards the nearer low-res neighbour, clamped at the border,
+// rows first) + channel 2 dy + dx for the three pixels other than (2i, 2j).
+__global__ void __launch_bounds__(256) k_d2s_out(const float* __restrict__ y4, int n, int h, int w,
+                                                  float* __restrict__ vis, float* __restrict__ logits) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)n * h * w;
+    if (idx >= total) return;
+    const int j = (int)(idx % w);
+    const long long t = idx / w;
+    const int i = (int)(t % h), f = (int)(t / h);
+    const float4* img = reinterpret_cast<const float4*>(y4) + (size_t)f * h * w;
+    const int im = max(i - 1, 0), ip = min(i + 1, h - 1);
+    const int jm = max(j - 1, 0), jp = min(j + 1, w - 1);
+    const float* c0 = reinterpret_cast<const float*>(img);
+    auto ch0 = [&](int r, int c) { return c0[((size_t)r * w + c) * 4]; };
+    const float4 me = img[(size_t)i * w + j];
+    const int cols[3] = {jm, j, jp};
+    float r0[3], r1[3];      // row-interpolated channel 0 at output rows 2i, 2i + 1
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float a = ch0(im, cols[q]), b = q == 1 ? me.x : ch0(i, cols[q]), c = ch0(ip, cols[q]);
+        r0[q] = 0.25f * a + 0.75f * b;
+        r1[q] = 0.75f * b + 0.25f * c;
+    }
+    float2 top, bot;
+    top.x = 0.25f * r0[0] + 0.75f * r0[1];
+    top.y = 0.75f * r0[1] + 0.25f * r0[2] + me.y;
+    bot.x = 0.25f * r1[0] + 0.75f * r1[1] + me.z;
+    bot.y = 0.75f * r1[1] + 0.25f * r1[2] + me.w;
+    const int W = 2 * w;
+    const size_t o = ((size_t)f * 2 * h + 2 * i) * W + 2 * j;
+    float2 vt, vb;
+    vt.x = 1.0f / (1.0f + __expf(-top.x));
+    vt.y = 1.0f / (1.0f + __expf(-top.y));
+    vb.x = 1.0f / (1.0f + __expf(-bot.x));
+    vb.y = 1.0f / (1.0f + __expf(-bot.y));
+    *reinterpret_cast<float2*>(vis + o) = vt;
+    *reinterpret_cast<float2*>(vis + o + W) = vb;
+    if (logits) {
+        *reinterpret_cast<float2*>(logits + o) = top;
+        *reinterpret_cast<float2*>(logits + o + W) = bot;
+    }
+}
+
 // 1x1 weights [C2][C1] float32 -> [NF2][NF1][64 lanes][4] storage type:
 // lane (co2 = l % 16, g = l / 16) element e holds W1[16 f2 + co2][16 f + 4 g + e].
 template <Dt D, int C1, int C2>
@@ -228,35 +312,39 @@ __global__ void k_pack1x1(const float* __restrict__ w, void* __restrict__ out) {
     reinterpret_cast<T*>(out)[idx] = from_f<T>(v);
 }
 
-// (cs, cu, sum, c1, c2, mode, float32 input, tile rows)
-#define NSM_PSTAGES(X)                                 \
-    X(4, 0, false, 16, 16, PoolOnly, true, 8)          \
-    X(16, 0, false, 32, 32, PoolSkip, false, 8)        \
-    X(32, 0, false, 64, 64, PoolSkip, false, 8)        \
-    X(64, 0, false, 128, 128, PoolSkip, false, 8)      \
-    X(128, 0, false, 256, 128, Store, false, 4)        \
-    X(32, 0, false, 64, 32, Store, false, 8)           \
-    X(128, 128, true, 128, 64, Store, false, 4)        \
-    X(64, 64, true, 64, 32, Store, false, 8)           \
-    X(32, 32, true, 32, 16, Store, false, 8)           \
-    X(0, 16, false, 16, 16, Head, false, 8)
+// (cs, cu, sum, c1, c2, mode, float32 input, tile rows, space-to-depth input)
+#define NSM_PSTAGES(X)                                        \
+    X(4, 0, false, 16, 16, PoolOnly, true, 8, false)          \
+    X(16, 0, false, 32, 32, PoolSkip, false, 8, false)        \
+    X(16, 0, false, 32, 32, PoolSkip, true, 8, true)          \
+    X(32, 0, false, 64, 64, PoolSkip, false, 8, false)        \
+    X(64, 0, false, 128, 128, PoolSkip, false, 8, false)      \
+    X(128, 0, false, 256, 128, Store, false, 4, false)        \
+    X(32, 0, false, 64, 32, Store, false, 8, false)           \
+    X(128, 128, true, 128, 64, Store, false, 4, false)        \
+    X(64, 64, true, 64, 32, Store, false, 8, false)           \
+    X(32, 32, true, 32, 16, Store, false, 8, false)           \
+    X(32, 32, true, 32, 16, D2S, false, 8, false)             \
+    X(0, 16, false, 16, 16, Head, false, 8, false)
 
 template <Dt D> constexpr const char* pdt_suffix() {
     return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : " f16");
 }
 
-#define NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)                                        \
+#define NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)                                  \
     (st.cs == CS_ && st.cu == CU_ && st.sum == SUM_ && st.c1 == C1_ && st.c2 == C2_ &&          \
-     st.mode == PMode::MODE_ && st.in_f32 == F32_)
+     st.mode == PMode::MODE_ && st.in_f32 == F32_ && st.s2d == S2D_)
 
 template <Dt D>
 hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* found) {
-#define NSM_PCASE(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_)                                     \
-    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)) {                                      \
+#define NSM_PCASE(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_)                               \
+    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)) {                                \
         *found = true;                                                                            \
         dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH_ - 1) / TH_, a.n);                             \
-        TraceScope ts("pconv " #CS_ "+" #CU_ "->" #C1_ "->" #C2_ " " #MODE_, pdt_suffix<D>(), s); \
-        k_pconv<D, F32_, CS_, CU_, SUM_, C1_, C2_, PMode::MODE_, TH_><<<grid, kThreads, 0, s>>>(a); \
+        TraceScope ts(S2D_ ? "pconv s2d " #CS_ "->" #C1_ "->" #C2_ " " #MODE_                     \
+                           : "pconv " #CS_ "+" #CU_ "->" #C1_ "->" #C2_ " " #MODE_,               \
+                      pdt_suffix<D>(), s);                                                        \
+        k_pconv<D, F32_, CS_, CU_, SUM_, C1_, C2_, PMode::MODE_, TH_, S2D_><<<grid, kThreads, 0, s>>>(a); \
         return hipGetLastError();                                                                 \
     }
     NSM_PSTAGES(NSM_PCASE)
@@ -267,8 +355,8 @@ hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* fo
 
 template <Dt D>
 bool ppack(const PStage& st, const float* w3, const float* w1, void* out, hipStream_t s, size_t* bytes) {
-#define NSM_PPACK(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_)                                     \
-    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)) {                                      \
+#define NSM_PPACK(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_)                               \
+    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)) {                                      \
         constexpr size_t b3 = packed_bytes<D, CS_, (SUM_ ? 0 : CU_), C1_>();                      \
         constexpr size_t b1 = (size_t)((C2_ + 15) / 16) * (C1_ / 16) * 64 * 4 * sizeof(typename DT<D>::T); \
         if (bytes) *bytes = ((b3 + 255) & ~(size_t)255) + b1;                                     \
@@ -289,8 +377,8 @@ bool ppack(const PStage& st, const float* w3, const float* w1, void* out, hipStr
 }  // namespace
 
 bool pconv_supported(const PStage& st) {
-#define NSM_PSUP(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_) \
-    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_)) return true;
+#define NSM_PSUP(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_) \
+    if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)) return true;
     NSM_PSTAGES(NSM_PSUP)
 #undef NSM_PSUP
     return false;
@@ -322,6 +410,14 @@ size_t pconv_w1_offset(const PStage& st, Dt dt) {
     const int NF2 = (st.c2 + 15) / 16, NF1 = st.c1 / 16;
     const size_t b1 = (size_t)NF2 * NF1 * 64 * 4 * (dt == Dt::F32 ? 4 : 2);
     return pconv_packed_bytes(st, dt) - b1;
+}
+
+hipError_t d2s_forward(const float* y4, int n, int h, int w, float* vis, float* logits, hipStream_t s) {
+    const long long total = (long long)n * h * w;
+    if (total <= 0) return hipSuccess;
+    TraceScope ts("d2s head", "", s);
+    k_d2s_out<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(y4, n, h, w, vis, logits);
+    return hipGetLastError();
 }
 
 hipError_t pconv_forward(const PStage& st, Dt dt, const PConvArgs& a, hipStream_t s) {

@@ -1,5 +1,7 @@
 """GPU parity of the paper's own network (3x3 + 1x1 per level, average
-pooling, sum skip, no level-0 skip) and of the PAPER4 features.
+pooling, sum skip, no level-0 skip), of its space-to-depth form (level 0
+removed, input read as 2x2 blocks, depth-to-space + bilinear head), and of
+the PAPER4 features.
 
 FP32: norm-wise 1e-5 on logits and visibility vs the FP64 oracle;
 BF16 / FP16: max |vis - vis_fp64| <= 2e-2.  Includes the 5-level net at the
@@ -16,19 +18,19 @@ pytestmark = pytest.mark.gpu
 P3, P5 = (16, 32, 64), (16, 32, 64, 128, 256)
 
 
-def _net(widths, dtype, flat):
+def _net(widths, dtype, flat, arch="paper"):
     from paper_2301_05262_amd.api import ShadowNet
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
-    m = ShadowNet(4, widths, dtype, arch="paper")
+    m = ShadowNet(4, widths, dtype, arch=arch)
     assert m.n_params == flat.size
     m.set_weights(torch.from_numpy(flat))
     return m
 
 
-def _weights(widths, seed):
+def _weights(widths, seed, s2d=False):
     rng = S.SplitMix64(seed)
     parts = []
-    for _, co, k, ci, _ in pn.conv_list(4, widths):
+    for _, co, k, ci, _ in (pn.conv_list_s2d if s2d else pn.conv_list)(4, widths):
         parts.append(rng.normals(co * k * k * ci) * np.sqrt(2.0 / (k * k * ci)))
         parts.append(rng.uniforms(co, -0.1, 0.1))
     return np.concatenate(parts).astype(np.float32)
@@ -58,6 +60,37 @@ def test_paper_net_random(widths, shape, dtype):
         e = np.abs(vis - ref["vis"]).max()
         print(f"[P{len(widths)} {shape} {dtype}] max |vis - fp64| {e:.2e}", flush=True)
         assert e <= 2e-2
+
+
+@pytest.mark.parametrize("widths,shape", [(P3, (2, 64, 96)), (P3, (1, 36, 52)), (P5, (1, 48, 80)),
+                                          (P5, (2, 144, 208))])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_paper_net_s2d_random(widths, shape, dtype):
+    """Level-1 tiles are 32 x 8: these shapes span several tiles with ragged
+    right and bottom edges (e.g. 104 = 3 x 32 + 8 columns at level 1)."""
+    n, h, w = shape
+    flat = _weights(widths, 44, s2d=True)
+    feat = S.SplitMix64(45).uniforms(n * h * w * 4, -1, 1).reshape(n, h, w, 4).astype(np.float32)
+    ref = pn.forward_s2d(4, widths, flat, feat)
+    vis, lg = _run(_net(widths, dtype, flat, arch="paper_s2d"), feat)
+    if dtype == "f32":
+        el = np.abs(lg - ref["logits"]).max() / np.abs(ref["logits"]).max()
+        ev = np.abs(vis - ref["vis"]).max() / np.abs(ref["vis"]).max()
+        print(f"[P{len(widths)}-s2d {shape} f32] norm-wise logits {el:.2e} vis {ev:.2e}", flush=True)
+        assert el <= 1e-5 and ev <= 1e-5
+    else:
+        e = np.abs(vis - ref["vis"]).max()
+        print(f"[P{len(widths)}-s2d {shape} {dtype}] max |vis - fp64| {e:.2e}", flush=True)
+        assert e <= 2e-2
+
+
+def test_paper_net_s2d_shape_errors():
+    from paper_2301_05262_amd.api import ShadowNet
+    m = ShadowNet(4, P5, "bf16", arch="paper_s2d")
+    assert m.n_params == pn.n_params(4, P5, s2d=True)
+    m.set_weights(torch.from_numpy(_weights(P5, 46, s2d=True)))
+    with pytest.raises(Exception):
+        m.forward(torch.zeros((1, 40, 80, 4), device="cuda"))      # 40 is not a multiple of 16
 
 
 def test_paper4_features_bit_exact():
@@ -95,4 +128,28 @@ def test_paper_net_full_size_on_paper4_features():
         else:
             e = np.abs(vis - ref["vis"]).max()
             print(f"[P5 1024x2048 bf16] max |vis - fp64| {e:.2e}", flush=True)
+            assert e <= 2e-2
+
+
+def test_paper_net_s2d_full_size_on_paper4_features():
+    """The space-to-depth 5-level net at 1024x2048 on PAPER4 features."""
+    from paper_2301_05262_amd.api import FeatureBuilder
+    sc = S.make_scene("objects60", 0)
+    fr = S.make_frame(sc, 2048, 1024, 2048, light_pos=(0.4, 3.2, -0.3), eye=(3.2, 1.5, 0.3),
+                      target=(0.0, -1.0, 0.0), light_radius=0.1)
+    feat = FeatureBuilder(sc)(fr, fs="paper4")["feat"]
+    torch.cuda.synchronize()
+    f_np = feat.cpu().numpy()
+    np.testing.assert_array_equal(f_np.view(np.uint32), oracle.build_features(sc, fr, fs="paper4")["feat"].view(np.uint32))
+    flat = _weights(P5, 47, s2d=True)
+    ref = pn.forward_s2d(4, P5, flat, f_np[None])
+    for dtype in ("f32", "bf16", "f16"):
+        vis, lg = _run(_net(P5, dtype, flat, arch="paper_s2d"), f_np[None])
+        if dtype == "f32":
+            el = np.abs(lg - ref["logits"]).max() / np.abs(ref["logits"]).max()
+            print(f"[P5-s2d 1024x2048 f32] norm-wise logits {el:.2e}", flush=True)
+            assert el <= 1e-5
+        else:
+            e = np.abs(vis - ref["vis"]).max()
+            print(f"[P5-s2d 1024x2048 {dtype}] max |vis - fp64| {e:.2e}", flush=True)
             assert e <= 2e-2
