@@ -258,7 +258,7 @@ def paper_net_section(S, torch, seed, steps):
     torch.cuda.synchronize()
     out["features_ms"] = 1e3 * (time.perf_counter() - t0) / steps
     out["paper_context"] = ("RTX 2080Ti, FP16: 17.3 ms for this network before the first-level "
-                            "optimisation and 5.84 ms after it (Sec. 4.5), 28 ms FP32")
+                            "optimisation and 5.84 ms after it (Sec. 3.5), 28 ms FP32")
     return out
 
 

@@ -6,7 +6,7 @@
  * view depth and normals, a single light-view depth map, the receiver's
  * depth towards the emitter and the emitter size -- composes a few
  * screen-space feature channels from them (Sec. 3.1, 3.2) and runs a compact
- * U-Net (Sec. 4.5) that outputs per-pixel shadow visibility in [0, 1].
+ * U-Net (Sec. 3.5) that outputs per-pixel shadow visibility in [0, 1].
  *
  * Three calls make up the path:
  *   nsm_build_features  light-view z-buffer, camera G-buffer, feature gather
@@ -77,9 +77,9 @@ typedef struct nsm_ctx nsm_ctx;
  *   ReLU + 2x2 max-pool for levels 0..L-2, bottleneck 3x3 conv + ReLU at
  *   level L-1, decoder bilinear x2 upsample, concat [skip, up], 3x3 conv +
  *   ReLU for levels L-2..0, then a 1x1 head to one channel and a sigmoid
- *   (one 3x3 conv per level and bilinear upsampling follow Sec. 4.5).
+ *   (one 3x3 conv per level and bilinear upsampling follow Sec. 3.5).
  *   Supported: c_in in {6, 8}; widths {8, 16} or {16, 32, 64}.
- * NSM_ARCH_PAPER: the paper's trimmed network (Sec. 4.5): per level a 3x3
+ * NSM_ARCH_PAPER: the paper's trimmed network (Sec. 3.5): per level a 3x3
  *   and a 1x1 conv (each + ReLU); 2x2 average pooling; decoder input
  *   up(y_{l+1}) + x_l (sum skip) for l >= 1 and up(y_1) alone at level 0;
  *   encoder level l: 3x3 C_{l-1} -> w_l, 1x1 w_l -> w_l; bottleneck: 3x3
@@ -89,7 +89,7 @@ typedef struct nsm_ctx nsm_ctx;
  *   list the convs in that order (each OHWI weights then biases).
  *   Supported: c_in = 4; widths {16, 32, 64} or {16, 32, 64, 128, 256}.
  * NSM_ARCH_PAPER_S2D: the paper's network after its first-level optimisation
- *   (Sec. 4.5): the level-0 convolutions are removed.  The input is read as
+ *   (Sec. 3.5): the level-0 convolutions are removed.  The input is read as
  *   2x2 blocks, (h, w, c_in) -> (h/2, w/2, 4 c_in), channel (2 dy + dx) c_in
  *   + c of block (i, j) being channel c of pixel (2i + dy, 2j + dx), and
  *   feeds the level-1 encoder (3x3 4 c_in -> w_1).  Levels 1..L-1 are those
@@ -170,7 +170,7 @@ nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n
  * Host only (no device call).  NSM_F32 runs the FP32 network; NSM_BF16 and
  * NSM_F16 run the precision form (activations and 3x3 weights stored in
  * that type, MFMA products accumulated in float32; the paper quantises its
- * network to half precision, Sec. 4.5).  Inputs and outputs of every call
+ * network to half precision, Sec. 3.5).  Inputs and outputs of every call
  * stay float32.  Decoder stages fold the bilinear x2 upsampling into their
  * weights away from the image border (four phase kernels per stage, formed
  * in float64 and rounded once to the storage type), so the upsampled tensor

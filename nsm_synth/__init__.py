@@ -20,6 +20,7 @@ from .scenes import (
     make_scene,
     make_train_window,
     make_batched_frames,
+    perturb_frame,
     workload_frame,
 )
 from .nets import NetDesc, U2, U3, U3_SOFT, layer_shapes, n_params, he_weights

@@ -2,7 +2,7 @@
 
 A descriptor names the input channel count and the per-level widths of a
 U-Net whose stages are one 3x3 convolution each (the paper trims every level
-to a single 3x3 convolution, Sec. 4.5), 2x2 max-pool between encoder levels,
+to a single 3x3 convolution, Sec. 3.5), 2x2 max-pool between encoder levels,
 bilinear x2 upsampling, skip concat [skip, up] and a 1x1 head with a sigmoid.
 
 The flat parameter vector lists the stages in execution order

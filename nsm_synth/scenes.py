@@ -334,6 +334,36 @@ def make_train_window(seed, window, frames=4, width=512, height=512, sm_size=102
     return scene, out
 
 
+def perturb_frame(scene, fr, seed, cam_scale=0.004, light_scale=0.004, size_scale=0.5):
+    """A jittered copy of a frame, the input of one perturbed network
+    instance of the perturbation loss (Sec. 3.3): the camera and the emitter
+    move by small random offsets that grow with their distance from the
+    scene and, for the emitter, with its size.
+
+    Offsets are uniform in a ball of radius cam_scale * |eye - c| for the
+    camera (keeping its aim point) and light_scale * |L - c| + size_scale *
+    r_e for the emitter, c the centre of the scene's bounding box.  The
+    scales are not given in the paper."""
+    rng = SplitMix64(seed).fork(0x9E27)
+    pts = scene.tris.reshape(-1, 3).astype(np.float64)
+    c = 0.5 * (pts.min(0) + pts.max(0))
+
+    def ball(radius):
+        while True:
+            v = np.array([rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1)])
+            if v @ v <= 1.0:
+                return radius * v
+
+    eye = fr.cam_pos.astype(np.float64)
+    target = eye + 3.0 * fr.cam_fwd.astype(np.float64)
+    L = fr.light_pos.astype(np.float64)
+    eye2 = eye + ball(cam_scale * np.linalg.norm(eye - c))
+    L2 = L + ball(light_scale * np.linalg.norm(L - c) + size_scale * fr.light_radius)
+    vfov = 2.0 * math.degrees(math.atan(fr.cam_tan_half_y))
+    return make_frame(scene, fr.width, fr.height, fr.sm_size, L2, eye2, target=target, vfov_deg=vfov,
+                      light_radius=fr.light_radius)
+
+
 def make_batched_frames(seed, n_frames=16, sizes=((1280, 720), (1920, 1080), (2560, 1440)),
                         sm_size=2048):
     """Mixed-size frames from scenes of ~20k-100k triangles, hard and soft lights."""

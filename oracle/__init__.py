@@ -7,7 +7,10 @@ leg may import this package.  It shares no code with the GPU library:
   z-buffer rasteriser, the feature gather with its depth-test mask, and the
   ray-cast visibility reference;
 * ``net.py`` (numpy float64): the network forward, its exact adjoint and a
-  storage-rounding emulation of the low-precision forward.
+  storage-rounding emulation of the low-precision forward;
+* ``paper_net.py``: the paper's own network and its space-to-depth form;
+* ``temporal.py``: the perturbation loss of Eq. 2 and the temporal
+  instability metric of Eq. 3 (its per-pixel part in ``nsm_oracle.c``).
 
 Parity status of every function is recorded in its test module; all of the
 functions here are pinned by the ``-m "not gpu"`` tests.
@@ -54,6 +57,8 @@ def lib():
         L.ora_raycast.argtypes = [vp, i32, vp, vp, i32, vp, f32, i32, ctypes.c_uint64, i32,
                                   ctypes.c_double, vp]
         L.ora_raycast.restype = i32
+        L.ora_temporal.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, f32, vp, vp, vp]
+        L.ora_temporal.restype = i32
         _lib = L
     return _lib
 

@@ -1,7 +1,7 @@
 """FP64 network oracle -- TEST INFRASTRUCTURE (tests, smoke check and the
 benchmark's CPU-baseline leg only; the product never calls this).
 
-The network is the trimmed U-Net of the paper (Sec. 4.5: one 3x3
+The network is the trimmed U-Net of the paper (Sec. 3.5: one 3x3
 convolution per level, bilinear upsampling instead of transposed
 convolutions, a sigmoid-bounded visibility output since visibility lies in
 [0, 1], supplemental Sec. 3) in the variant measured here: 2x2 max-pool

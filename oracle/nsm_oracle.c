@@ -513,3 +513,112 @@ int ora_raycast(const float *tris, int n_tris, const float *pos, const uint8_t *
     free(b.nodes);
     return 0;
 }
+
+/* ------------------------------------------------------ temporal metric
+ * Temporal instability of Eq. 3 for one pair of consecutive frames: the sum
+ * over the current frame's pixels p of exp(alpha * D(p)) - 1, where
+ * D(p) = |I_t(p) - I_{t-1}(m(p))| and m(p) is the motion-compensated pixel
+ * of the previous frame.  Per pixel (i, j) of the current frame:
+ *   1. background (empty key) -> no term;
+ *   2. receiver P and camera-facing normal n of the current frame, as in
+ *      the gather (float64 ray / plane intersection, rounded to float32);
+ *   3. P projected with the previous camera matrix (float32, products and
+ *      sums in the written order), c_w <= 1e-6 or outside the screen ->
+ *      rejected; m(p) = (floor(sx), floor(sy));
+ *   4. previous key at m(p) empty -> rejected;
+ *   5. previous receiver P' and normal n' at m(p) (previous camera);
+ *   6. depth test: view depths of P and P' along the previous camera axis,
+ *      rejected when |dv - dv'| > depth_tol * dv';
+ *   7. normal test: rejected when n . n' < cos_tol;
+ *   8. D = |I_t(p) - I_{t-1}(m(p))|, term = exp(alpha D) - 1 (float64).
+ * Outputs the float64 sum of the terms, the number of pixels that passed,
+ * and optionally per pixel D or a negative code: -1 background,
+ * -2 off-screen, -3 empty previous pixel, -4 depth, -5 normal.
+ */
+static int cam_receiver(const float *tris, const float *normals, int n_tris, const float *fp,
+                        uint64_t key, int i, int j, int w, int h, float *P, float *n) {
+    const float *E = fp + 40, *fw = fp + 43, *rt = fp + 46, *up = fp + 49;
+    const float tanx = fp[52], tany = fp[53];
+    if (key == EMPTY_KEY) return 0;
+    uint32_t t = (uint32_t)(key & 0xFFFFFFFFu);
+    if ((int)t >= n_tris) return 0;
+    double ndcx = (2.0 * ((double)i + 0.5)) / (double)w - 1.0;
+    double ndcy = (2.0 * ((double)j + 0.5)) / (double)h - 1.0;
+    double ax = ndcx * (double)tanx, ay = ndcy * (double)tany;
+    double D[3];
+    for (int k = 0; k < 3; ++k) D[k] = ((double)fw[k] + ax * (double)rt[k]) + ay * (double)up[k];
+    const float *V0 = tris + 9 * (size_t)t;
+    const float *N = normals + 3 * (size_t)t;
+    double num = (double)N[0] * ((double)V0[0] - (double)E[0]);
+    num = num + (double)N[1] * ((double)V0[1] - (double)E[1]);
+    num = num + (double)N[2] * ((double)V0[2] - (double)E[2]);
+    double den = (double)N[0] * D[0];
+    den = den + (double)N[1] * D[1];
+    den = den + (double)N[2] * D[2];
+    if (den == 0.0) return 0;
+    double tt = num / den;
+    for (int k = 0; k < 3; ++k) P[k] = (float)((double)E[k] + tt * D[k]);
+    n[0] = N[0]; n[1] = N[1]; n[2] = N[2];
+    float vx = E[0] - P[0], vy = E[1] - P[1], vz = E[2] - P[2];
+    float s = n[0] * vx + n[1] * vy;
+    s = s + n[2] * vz;
+    if (s < 0.0f) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }
+    return 1;
+}
+
+static float view_depth(const float *fp, const float *P) {
+    const float *E = fp + 40, *fw = fp + 43;
+    float dv = (P[0] - E[0]) * fw[0] + (P[1] - E[1]) * fw[1];
+    return dv + (P[2] - E[2]) * fw[2];
+}
+
+int ora_temporal(const float *tris, const float *normals, int n_tris, const float *fp_prev,
+                 const float *fp_cur, const uint64_t *gbuf_prev, const uint64_t *gbuf_cur,
+                 const float *vis_prev, const float *vis_cur, int w, int h, float alpha,
+                 float depth_tol, float cos_tol, double *sum_out, int64_t *valid_out, float *d_out) {
+    if (!tris || !normals || !fp_prev || !fp_cur || !gbuf_prev || !gbuf_cur || !vis_prev ||
+        !vis_cur || !sum_out || !valid_out || w <= 0 || h <= 0)
+        return 1;
+    const float *mprev = fp_prev + 24;
+    double total = 0.0;
+    int64_t valid = 0;
+    for (int j = 0; j < h; ++j) {
+        for (int i = 0; i < w; ++i) {
+            size_t p = (size_t)j * (size_t)w + (size_t)i;
+            float code = -1.0f;
+            float P[3], n[3], Pq[3], nq[3];
+            if (cam_receiver(tris, normals, n_tris, fp_cur, gbuf_cur[p], i, j, w, h, P, n)) {
+                float c[4];
+                clip_vertex(mprev, P, c);
+                code = -2.0f;
+                if (c[3] > 1e-6f) {
+                    float nx = c[0] / c[3], ny = c[1] / c[3];
+                    float sx = (nx * 0.5f + 0.5f) * (float)w;
+                    float sy = (ny * 0.5f + 0.5f) * (float)h;
+                    if (sx >= 0.0f && sx < (float)w && sy >= 0.0f && sy < (float)h) {
+                        int iq = (int)floorf(sx), jq = (int)floorf(sy);
+                        size_t q = (size_t)jq * (size_t)w + (size_t)iq;
+                        code = -3.0f;
+                        if (cam_receiver(tris, normals, n_tris, fp_prev, gbuf_prev[q], iq, jq, w, h, Pq, nq)) {
+                            float dv = view_depth(fp_prev, P), dq = view_depth(fp_prev, Pq);
+                            float cs = n[0] * nq[0] + n[1] * nq[1];
+                            cs = cs + n[2] * nq[2];
+                            if (fabsf(dv - dq) > depth_tol * dq) code = -4.0f;
+                            else if (cs < cos_tol) code = -5.0f;
+                            else {
+                                float D = fabsf(vis_cur[p] - vis_prev[q]);
+                                total += exp((double)alpha * (double)D) - 1.0;
+                                valid++;
+                                code = D;
+                            }
+                        }
+                    }
+                }
+            }
+            if (d_out) d_out[p] = code;
+        }
+    }
+    *sum_out = total;
+    *valid_out = valid;
+    return 0;
+}

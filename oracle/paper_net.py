@@ -1,6 +1,6 @@
 """FP64 oracle of the paper's own network ("P-net") -- TEST INFRASTRUCTURE.
 
-The architecture the paper describes (Sec. 4.5): per level one 3x3 and one
+The architecture the paper describes (Sec. 3.5): per level one 3x3 and one
 1x1 convolution instead of a double 3x3; bilinear upsampling; skip merged by
 an algebraic sum; average pooling; no skip connection at level 0; a 1x1
 output convolution and a bounded (sigmoid) visibility.  The channel plan
@@ -19,7 +19,7 @@ Flat parameters: the convolutions in the order above (encoder levels, then
 bottleneck, then decoder levels from L-2 down to 0, then the output conv),
 each OHWI weights followed by biases.
 
-The space-to-depth form (Sec. 4.5, the optimisation of the first level):
+The space-to-depth form (Sec. 3.5, the optimisation of the first level):
 the level-0 convolutions are gone.  The input is rearranged into 2x2 blocks,
 (H, W, c) -> (H/2, W/2, 4c), and fed straight to the level-1 encoder.  The
 last decoder level (level 1) ends in a 1x1 output convolution to four

@@ -9,7 +9,7 @@ channel sensitivity.
   x_{a,b} = z_f tan(theta -/+ theta_delta) - r_e with
   theta_delta = asin(r_s / sqrt(z_m^2 + r_e^2)) and
   theta = atan((r_e (z_f - z_m) / z_m + r_e) / z_f); the width is x_a + x_b.
-* Depth rule (Sec. 4.6): halving the resolution per level with 3x3 kernels
+* Depth rule (Sec. 3.6): halving the resolution per level with 3x3 kernels
   gives an effective receptive field of 3 * 2^l pixels for l levels, so
   l = log2(p_w / 3) levels cover a penumbra of p_w pixels; p_w is taken as
   the 95th percentile of the per-pixel screen-space widths.

@@ -1,6 +1,6 @@
 // Backward (adjoint) kernels of the shadow U-Net, float32 -- the
 // differentiation form.  The paper trains its network with gradient descent
-// (Sec. 4.3, 5); here every stage has a hand-written adjoint:
+// (Sec. 3.3; supplemental Sec. 5); here every stage has a hand-written adjoint:
 //
 //   head       g = dvis * s * (1 - s) with s = sigmoid(logit); the 1x1 head's
 //              weight / bias gradients and the gradient reaching the last

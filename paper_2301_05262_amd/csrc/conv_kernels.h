@@ -1,6 +1,6 @@
 // Fused 3x3 convolution stages of the shadow U-Net as MFMA implicit GEMM.
 //
-// The network (paper Sec. 4.5) is a U-Net trimmed to one 3x3 convolution per
+// The network (paper Sec. 3.5) is a U-Net trimmed to one 3x3 convolution per
 // level with bilinear upsampling; the paper's measurements (supplemental
 // Sec. 3, layer-wise table) show its runtime follows the size of the
 // temporary buffers rather than the flop count, so every stage here is one

@@ -1,6 +1,6 @@
 // Decoder stages with the bilinear x2 upsampling folded into the weights.
 //
-// A decoder stage (paper Sec. 4.5) convolves the concatenation [skip, up(low)]
+// A decoder stage (paper Sec. 3.5) convolves the concatenation [skip, up(low)]
 // with a 3x3 kernel, where up() is bilinear x2 with half-pixel centres: row y
 // of the upsampled image is 1/4 of low row (y-1)/2 and 3/4 of the next one
 // for even y (the reverse for odd y), clamped to the low image.  Both maps are

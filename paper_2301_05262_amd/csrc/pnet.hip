@@ -1,4 +1,4 @@
-// Stages of the paper's own network (Sec. 4.5): per level one 3x3 conv and
+// Stages of the paper's own network (Sec. 3.5): per level one 3x3 conv and
 // one 1x1 conv (each + ReLU), average pooling, skip merged by a sum, no
 // level-0 skip, a 1x1 output conv and a sigmoid.
 //
@@ -11,7 +11,7 @@
 // per-element for v_mfma_f32_16x16x4_f32.  Nothing of the 3x3 output
 // touches memory.  Epilogues: store; 2x2 average pool (with or without the
 // full-resolution skip store); the output 1x1 + sigmoid; the output 1x1 to
-// four channels of the space-to-depth form (Sec. 4.5), whose depth-to-space
+// four channels of the space-to-depth form (Sec. 3.5), whose depth-to-space
 // head k_d2s_out then forms the full-resolution visibility.  The first
 // encoder stage of that form reads its input through space-to-depth in the
 // halo load, so the rearranged input never exists in memory.
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     }
 }
 
-// Depth-to-space head of the space-to-depth form (Sec. 4.5).  One thread per
+// Depth-to-space head of the space-to-depth form (Sec. 3.5).  One thread per
 // low-resolution pixel (i, j) writes the 2x2 block (2i + dy, 2j + dx):
 // logit = bilinear x2 of channel 0 (the taps of the decoder's upsampling:
 // 0.25 / 0.75 towards the nearer low-res neighbour, clamped at the border,

@@ -1,4 +1,4 @@
-"""Pins for the FP64 network oracle (trimmed U-Net, paper Sec. 4.5).
+"""Pins for the FP64 network oracle (trimmed U-Net, paper Sec. 3.5).
 
 Each step is checked against something other than itself: library routines
 (torch float64 conv2d, max_pool2d, bilinear interpolate with half-pixel

@@ -1,4 +1,4 @@
-"""Pins for the oracle of the paper's own network (Sec. 4.5).
+"""Pins for the oracle of the paper's own network (Sec. 3.5).
 
 The channel plan is pinned by the numbers the paper prints in its
 layer-wise table (supplemental Sec. 3) and cost table (supplemental
