@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--batched", type=int, default=1, help="also time the 16-frame graph batch")
     ap.add_argument("--paper-net", type=int, default=1, help="also time the paper's 5-level net")
     ap.add_argument("--training", type=int, default=1, help="also time the 32-frame FP32 training step")
+    ap.add_argument("--temporal", type=int, default=1,
+                    help="also time the perturbation-loss training step and the temporal metric")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="end with one plain 256 MiB device copy (the scale for HBM byte counters)")
     return ap.parse_args()
@@ -202,6 +204,82 @@ def training_section(S, torch, seed, steps):
     return {"workload": "soft_train_512", "frames": n, "ms_per_step": ms, "dtype": "f32",
             "tflops_effective": flop / (ms * 1e-3) / 1e12, "flop_per_step": flop,
             "ideal_ms_at_fp32_mfma_peak": flop / MFMA_PEAK["f32"] * 1e3}
+
+
+def temporal_section(S, torch, seed, steps):
+    """The temporal-stability parts (Sec. 3.3-3.4).
+
+    perturb_train: one training step with the perturbation loss of Eq. 2 on
+    8 samples of 512x512: SOFT8 features of each sample's frame and of 3
+    perturbed copies (32 frames), one FP32 forward over all 32, the loss and
+    its gradient, and the backward through the 8 unperturbed instances only.
+    metric_1080p: one consecutive frame pair of Eq. 3 at 1920x1080 (reprojection,
+    depth / normal rejection, float64 sum)."""
+    import paper_2301_05262_amd as nsm
+    from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet, TemporalMetric, perturbation_loss
+    wins = [S.make_train_window(seed, k, frames=1) for k in range(8)]
+    jobs = []
+    for k, (sc, frs) in enumerate(wins):
+        b = FeatureBuilder(sc)
+        jobs += [(b, fr) for fr in [frs[0]] + [S.perturb_frame(sc, frs[0], 1000 * k + i) for i in range(3)]]
+    feat = torch.empty((32, 512, 512, 8), dtype=torch.float32, device="cuda")
+    bufs = [b(fr, soft=True) for b, fr in jobs]
+    rng = S.SplitMix64(seed + 11)
+    target = torch.from_numpy(rng.uniforms(8 * 512 * 512, 0.0, 1.0).reshape(8, 512, 512).astype(np.float32)).cuda()
+    net = ShadowNet(8, S.U3_SOFT.widths, "f32")
+    net.set_weights(torch.from_numpy(S.he_weights(S.U3_SOFT, seed)))
+    dw = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    x0 = torch.empty((8, 512, 512, 8), dtype=torch.float32, device="cuda")
+
+    def step():
+        for k, (b, fr) in enumerate(jobs):
+            b(fr, soft=True, out=bufs[k])
+            feat[k].copy_(bufs[k]["feat"])
+        vis = net.forward(feat).view(8, 4, 512, 512)
+        _, dvis0 = perturbation_loss(vis, target)
+        x0.copy_(feat.view(8, 4, 512, 512, 8)[:, 0])
+        net.backward(x0, dvis0, dw_out=dw)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b) / steps
+
+    sc, frames = S.make_train_window(seed, 0, frames=2, width=1920, height=1080, sm_size=2048)
+    fb = FeatureBuilder(sc)
+    g0, g1 = fb(frames[0])["gbuf"].clone(), fb(frames[1])["gbuf"].clone()
+    v0 = torch.from_numpy(rng.uniforms(1080 * 1920, 0, 1).reshape(1080, 1920).astype(np.float32)).cuda()
+    v1 = torch.from_numpy(rng.uniforms(1080 * 1920, 0, 1).reshape(1080, 1920).astype(np.float32)).cuda()
+    metric = TemporalMetric(sc, 1080, 1920)
+    for _ in range(5):
+        metric.add(frames[0], frames[1], g0, g1, v0, v1)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps * 4):
+        metric.add(frames[0], frames[1], g0, g1, v0, v1)
+    b.record()
+    torch.cuda.synchronize()
+    pair_ms = a.elapsed_time(b) / (steps * 4)
+    nsm.nsm_trace_read()
+    nsm.nsm_trace_enable(True)
+    for _ in range(steps):
+        metric.add(frames[0], frames[1], g0, g1, v0, v1)
+    torch.cuda.synchronize()
+    per = {}
+    for name, ms in nsm.nsm_trace_read(1 << 16):
+        per.setdefault(name, []).append(ms)
+    nsm.nsm_trace_enable(False)
+    return {"perturb_train": {"workload": "soft_perturb_train_512", "samples": 8, "perturbations": 3,
+                              "forward_frames": 32, "backward_frames": 8, "ms_per_step": train_ms,
+                              "dtype": "f32"},
+            "metric_1080p": {"ms_per_pair": pair_ms,
+                             "kernels_us": {k: 1e3 * float(np.mean(v)) for k, v in per.items()}}}
 
 
 def _time_net(torch, nsm, net, feat, vis, steps):
@@ -404,6 +482,12 @@ def main():
         training = training_section(S, torch, args.seed, steps=5)
         print(f"[bench] training step (32 x 512^2, fp32): {training['ms_per_step']:.2f} ms",
               file=sys.stderr, flush=True)
+    temporal = None
+    if args.temporal:
+        temporal = temporal_section(S, torch, args.seed, steps=5)
+        print(f"[bench] perturbation-loss training step (8 x (1+3) x 512^2, fp32): "
+              f"{temporal['perturb_train']['ms_per_step']:.2f} ms; Eq. 3 metric 1080p pair: "
+              f"{temporal['metric_1080p']['ms_per_pair'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     paper_net = None
     if args.paper_net:
         paper_net = paper_net_section(S, torch, args.seed, steps=50)
@@ -421,7 +505,7 @@ def main():
                    "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
                    "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
         "forms": results, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
-        "paper_net": paper_net, "training": training,
+        "paper_net": paper_net, "training": training, "temporal": temporal,
     }
     print(json.dumps(line))
     sys.stdout.flush()

@@ -13,6 +13,9 @@
  *   nsm_forward         U-Net inference (FP32, or BF16/FP16 on MFMA)
  *   nsm_backward        gradient of the visibility w.r.t. the weights and
  *                       the features (the differentiation form; FP32)
+ * and two around it for temporal stability:
+ *   nsm_perturbation_loss     Eq. 2's loss and its gradient through x_0
+ *   nsm_temporal_instability  Eq. 3's metric over a pair of frames
  *
  * Conventions shared by every call:
  *   - Every tensor argument is a device pointer owned by the caller unless
@@ -214,6 +217,68 @@ nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, flo
 nsm_status nsm_backward(nsm_ctx *ctx, const float *feat, const float *dvis, int n, int h, int w,
                         float *dw_out, int accumulate, float *dfeat_out, void *workspace,
                         size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------- temporal stability
+ * nsm_perturbation_loss -- the perturbation loss of paper Sec. 3.3, Eq. 2,
+ * with its per-pixel term L(y, y~) = alpha * mean |y - y~| (the perceptual
+ * term is not part of this library).  For each of n samples, x_0 is the
+ * network output on the unperturbed input, x_1..x_p the outputs on p
+ * perturbed inputs and x~ the target:
+ *     loss = alpha / (n h w) * sum ( |x_0 - x~| + sum_i |x_0 - x_i| )
+ * and its gradient with respect to x_0 alone (x_1..x_p are held constant,
+ * as in the paper only one instance back-propagates), sgn(0) taken as 0:
+ *     dvis0 = alpha / (n h w) * ( sgn(x_0 - x~) + sum_i sgn(x_0 - x_i) ).
+ *   vis        [n][1+p][h][w] float32 (x_0 first in every sample).
+ *   target     [n][h][w] float32.
+ *   p          0..16 (the paper uses 3).
+ *   loss_out   [1] float64, overwritten.
+ *   dvis0_out  [n][h][w] float32, overwritten; feed it to nsm_backward with
+ *              the x_0 features.
+ * The sums are float64 and deterministic (fixed reduction order).
+ * Errors: NSM_E_SHAPE for n, p, h, w out of range; NSM_E_WORKSPACE below
+ * nsm_perturbation_loss_workspace_bytes. */
+nsm_status nsm_perturbation_loss_workspace_bytes(int n, int p, int h, int w, size_t *bytes);
+nsm_status nsm_perturbation_loss(const float *vis, const float *target, int n, int p, int h, int w,
+                                 float alpha, double *loss_out, float *dvis0_out, void *workspace,
+                                 size_t ws_bytes, void *stream);
+
+/* nsm_temporal_instability -- one frame pair of the temporal-instability
+ * metric of paper Sec. 3.4, Eq. 3:
+ *     E = (1/P) sum_{p,t} [exp(alpha D_t(p)) - 1],  D_t(p) = |I_t(p) - I_{t-1}(m(p))|.
+ * Adds this pair's sum of exp(alpha D) - 1 to acc_out[0] and its number of
+ * contributing pixels to acc_out[1] (or overwrites both when accumulate is
+ * 0); call once per consecutive pair and divide acc_out[0] by P (the paper's
+ * normaliser, the total pixel count, w h (T - 1) for T frames).
+ * Per pixel p = (i, j) of the current frame:
+ *   - background (empty key) contributes nothing;
+ *   - the receiver P (pixel-centre ray / key triangle plane, float64
+ *     rounded to float32) and its camera-facing face normal n;
+ *   - m(p): P projected with prev->m_cam (float32, products and sums in
+ *     order, as the rasteriser's vertex transform), c_w <= 1e-6 or outside
+ *     [0, w) x [0, h) rejects, else the pixel (floor(sx), floor(sy));
+ *   - rejected when the previous key at m(p) is empty, when the view depths
+ *     of P and of the previous receiver P' along prev's camera axis differ
+ *     by more than depth_tol * depth(P'), or when n . n' < cos_tol.
+ * Scenes are static (camera and light move), so reprojecting P is the
+ * motion-vector lookup.  The paper does not give the thresholds; 0.01 and
+ * 0.9 are this library's defaults in the Python binding.
+ *   tris, tri_normals  the scene, as in nsm_build_features.
+ *   gbuf_prev/cur      [h][w] camera keys of the two frames (as written by
+ *                      nsm_build_features).
+ *   vis_prev/cur       [h][w] float32 network outputs I_{t-1}, I_t.
+ *   acc_out            [2] float64 (device).
+ *   d_out              [h][w] float32 or NULL: D(p) where the pixel counted,
+ *                      else -1 background, -2 off-screen, -3 empty previous
+ *                      pixel, -4 depth, -5 normal.
+ * Deterministic. Errors: NSM_E_SHAPE for h, w out of range;
+ * NSM_E_WORKSPACE below nsm_temporal_workspace_bytes. */
+nsm_status nsm_temporal_workspace_bytes(int h, int w, size_t *bytes);
+nsm_status nsm_temporal_instability(const float *tris, const float *tri_normals, int n_tris,
+                                    const nsm_frame_params *prev, const nsm_frame_params *cur,
+                                    const uint64_t *gbuf_prev, const uint64_t *gbuf_cur,
+                                    const float *vis_prev, const float *vis_cur, int h, int w, float alpha,
+                                    float depth_tol, float cos_tol, int accumulate, double *acc_out,
+                                    float *d_out, void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------- diagnostics
  * Per-kernel timing.  While enabled (process-wide), every kernel the

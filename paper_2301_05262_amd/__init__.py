@@ -24,6 +24,10 @@ from ._lib import (  # noqa: F401
     frame_params,
     nsm_trace_enable,
     nsm_trace_read,
+    nsm_perturbation_loss_workspace_bytes,
+    nsm_perturbation_loss,
+    nsm_temporal_workspace_bytes,
+    nsm_temporal_instability,
 )
 
 

@@ -23,6 +23,8 @@ EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
     "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
     "nsm_forward", "nsm_backward", "nsm_trace_enable", "nsm_trace_read",
+    "nsm_perturbation_loss_workspace_bytes", "nsm_perturbation_loss", "nsm_temporal_workspace_bytes",
+    "nsm_temporal_instability",
 ]
 
 
@@ -77,6 +79,12 @@ def load():
         "nsm_forward": ([vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "nsm_backward": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
         "nsm_trace_enable": ([i32], i32),
+        "nsm_perturbation_loss_workspace_bytes": ([i32, i32, i32, i32, psz], i32),
+        "nsm_perturbation_loss": ([vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp, sz, vp], i32),
+        "nsm_temporal_workspace_bytes": ([i32, i32, psz], i32),
+        "nsm_temporal_instability": ([vp, vp, i32, ctypes.POINTER(FrameParams), ctypes.POINTER(FrameParams),
+                                      vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, i32, vp, vp, vp, sz, vp], i32),
         "nsm_trace_read": ([i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_int)], i32),
     }
@@ -218,3 +226,35 @@ def nsm_trace_read(max_records=4096):
     for i in range(min(n.value, max_records)):
         out.append((raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode(), float(ms[i])))
     return out
+
+
+def nsm_perturbation_loss_workspace_bytes(n, p, h, w):
+    out = ctypes.c_size_t()
+    _check(load().nsm_perturbation_loss_workspace_bytes(n, p, h, w, ctypes.byref(out)),
+           "nsm_perturbation_loss_workspace_bytes")
+    return out.value
+
+
+def nsm_perturbation_loss(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, workspace, ws_bytes,
+                          stream=None):
+    _check(load().nsm_perturbation_loss(_ptr(vis), _ptr(target), n, p, h, w, float(alpha), _ptr(loss_out),
+                                        _ptr(dvis0_out), _ptr(workspace), ws_bytes, _stream(stream)),
+           "nsm_perturbation_loss")
+
+
+def nsm_temporal_workspace_bytes(h, w):
+    out = ctypes.c_size_t()
+    _check(load().nsm_temporal_workspace_bytes(h, w, ctypes.byref(out)), "nsm_temporal_workspace_bytes")
+    return out.value
+
+
+def nsm_temporal_instability(tris, tri_normals, n_tris, fp_prev, fp_cur, gbuf_prev, gbuf_cur, vis_prev,
+                             vis_cur, h, w, alpha, depth_tol, cos_tol, accumulate, acc_out, d_out,
+                             workspace, ws_bytes, stream=None):
+    a, b = frame_params(fp_prev), frame_params(fp_cur)
+    _check(load().nsm_temporal_instability(_ptr(tris), _ptr(tri_normals), n_tris, ctypes.byref(a),
+                                           ctypes.byref(b), _ptr(gbuf_prev), _ptr(gbuf_cur), _ptr(vis_prev),
+                                           _ptr(vis_cur), h, w, float(alpha), float(depth_tol),
+                                           float(cos_tol), int(accumulate), _ptr(acc_out), _ptr(d_out),
+                                           _ptr(workspace), ws_bytes, _stream(stream)),
+           "nsm_temporal_instability")

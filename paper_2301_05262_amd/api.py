@@ -136,3 +136,58 @@ class NSMForward(torch.autograd.Function):
         dw, df = net.backward(feat.detach().contiguous(), dvis.contiguous(),
                               want_dfeat=ctx.needs_input_grad[0])
         return (df if ctx.needs_input_grad[0] else None), dw, None
+
+
+def perturbation_loss(vis, target, alpha=0.9, stream=None):
+    """Perturbation loss of Eq. 2 (per-pixel L1 term) and its gradient
+    through x_0 only.
+
+    vis [N, 1+p, H, W] float32 (x_0 first), target [N, H, W] float32 ->
+    (loss: float64 tensor [1], dvis0: float32 [N, H, W])."""
+    if vis.dim() == 3:
+        vis, target = vis.unsqueeze(0), target.unsqueeze(0)
+    n, q, h, w = vis.shape
+    if (vis.dtype != torch.float32 or target.dtype != torch.float32 or not vis.is_contiguous()
+            or not target.is_contiguous() or tuple(target.shape) != (n, h, w)):
+        raise ValueError("vis must be contiguous float32 [N,1+p,H,W] and target [N,H,W]")
+    need = _lib.nsm_perturbation_loss_workspace_bytes(n, q - 1, h, w)
+    ws = torch.empty(need, dtype=torch.uint8, device=vis.device)
+    loss = torch.empty(1, dtype=torch.float64, device=vis.device)
+    dvis0 = torch.empty((n, h, w), dtype=torch.float32, device=vis.device)
+    _lib.nsm_perturbation_loss(vis, target, n, q - 1, h, w, alpha, loss, dvis0, ws, ws.numel(), stream)
+    return loss, dvis0
+
+
+class TemporalMetric:
+    """Temporal instability of Eq. 3 over a sequence of frames of one scene,
+    accumulated on the device pair by pair."""
+
+    def __init__(self, scene, height, width, alpha=3.0, depth_tol=0.01, cos_tol=0.9, device=None):
+        dev = _dev(device)
+        self.tris = torch.from_numpy(scene.tris).to(dev).contiguous()
+        self.normals = torch.from_numpy(scene.normals).to(dev).contiguous()
+        self.n_tris = int(scene.tris.shape[0])
+        self.h, self.w = int(height), int(width)
+        self.alpha, self.depth_tol, self.cos_tol = alpha, depth_tol, cos_tol
+        self.acc = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.pairs = 0
+        self._ws = torch.empty(_lib.nsm_temporal_workspace_bytes(self.h, self.w), dtype=torch.uint8,
+                               device=dev)
+
+    def reset(self):
+        self.acc.zero_()
+        self.pairs = 0
+
+    def add(self, fr_prev, fr_cur, gbuf_prev, gbuf_cur, vis_prev, vis_cur, d_out=None, stream=None):
+        """Adds one consecutive pair; d_out ([H, W] float32) receives D or a
+        negative rejection code per pixel."""
+        _lib.nsm_temporal_instability(self.tris, self.normals, self.n_tris, fr_prev, fr_cur, gbuf_prev,
+                                      gbuf_cur, vis_prev.contiguous(), vis_cur.contiguous(), self.h, self.w,
+                                      self.alpha, self.depth_tol, self.cos_tol, 1, self.acc, d_out,
+                                      self._ws, self._ws.numel(), stream)
+        self.pairs += 1
+
+    def value(self):
+        """E = sum / (W H (T - 1)) and the number of contributing pixels."""
+        s, k = self.acc.tolist()
+        return s / (self.w * self.h * max(self.pairs, 1)), int(k)

@@ -2,7 +2,7 @@
 
 Each ``csrc/*.hip`` file is compiled to an object in ``_build/`` (in
 parallel), then all are linked into ``paper_2301_05262_amd/libnsm.so``.
-The rasteriser/gather file is compiled without floating-point contraction
+The rasteriser/gather and temporal files are compiled without floating-point contraction
 so that every product and sum is rounded on its own; float32 divide and
 square root are the correctly rounded forms.
 """
@@ -25,7 +25,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
-EXACT = {"raster.hip": ["-ffp-contract=off"]}
+EXACT = {"raster.hip": ["-ffp-contract=off"], "temporal.hip": ["-ffp-contract=off"]}
 
 
 def sources():

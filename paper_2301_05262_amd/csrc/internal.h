@@ -68,6 +68,22 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
                   const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s);
 
+// ------------------------------------------------------ temporal stability
+// One camera as the receiver reconstruction and the reprojection see it.
+struct CamParams {
+    float m[16];                 // world -> clip, row-major
+    float E[3], fwd[3], right[3], up[3];
+    float tanx, tany;
+};
+size_t perturb_loss_workspace_bytes(long long npx);
+hipError_t perturb_loss(const float* vis, const float* target, int n, int p, int h, int w, float alpha,
+                        double* loss, float* dvis0, void* ws, hipStream_t s);
+size_t temporal_workspace_bytes(int h, int w);
+hipError_t temporal_pair(const float* tris, const float* normals, int n_tris, const CamParams& prev,
+                         const CamParams& cur, const uint64_t* gprev, const uint64_t* gcur, const float* vprev,
+                         const float* vcur, int h, int w, float alpha, float depth_tol, float cos_tol,
+                         int accumulate, double* acc_out, float* d_out, void* ws, hipStream_t s);
+
 // --------------------------------------------------------------- network
 enum class Dt { F32 = 0, BF16 = 1, F16 = 2 };
 

@@ -619,4 +619,72 @@ nsm_status nsm_backward(nsm_ctx* ctx, const float* feat, const float* dvis, int 
     return NSM_OK;
 }
 
+
+// ------------------------------------------------------ temporal stability
+constexpr int kMaxPerturb = 16;
+
+nsm_status nsm_perturbation_loss_workspace_bytes(int n, int p, int h, int w, size_t* bytes) {
+    if (!bytes) return NSM_E_INVALID_ARG;
+    if (n < 1 || n > kMaxFrames || p < 0 || p > kMaxPerturb || h < 1 || w < 1 || h > kMaxImage ||
+        w > kMaxImage)
+        return NSM_E_SHAPE;
+    *bytes = perturb_loss_workspace_bytes((long long)n * h * w);
+    return NSM_OK;
+}
+
+nsm_status nsm_perturbation_loss(const float* vis, const float* target, int n, int p, int h, int w,
+                                 float alpha, double* loss_out, float* dvis0_out, void* workspace,
+                                 size_t ws_bytes, void* stream) {
+    if (!vis || !target || !loss_out || !dvis0_out) return NSM_E_INVALID_ARG;
+    if (n < 1 || n > kMaxFrames || p < 0 || p > kMaxPerturb || h < 1 || w < 1 || h > kMaxImage ||
+        w > kMaxImage)
+        return NSM_E_SHAPE;
+    if (!workspace || ws_bytes < perturb_loss_workspace_bytes((long long)n * h * w)) return NSM_E_WORKSPACE;
+    if (!device_ok()) return NSM_E_DEVICE;
+    if (perturb_loss(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, workspace,
+                     reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+        return NSM_E_LAUNCH;
+    return NSM_OK;
+}
+
+nsm_status nsm_temporal_workspace_bytes(int h, int w, size_t* bytes) {
+    if (!bytes) return NSM_E_INVALID_ARG;
+    if (h < 1 || w < 1 || h > kMaxImage || w > kMaxImage) return NSM_E_SHAPE;
+    *bytes = temporal_workspace_bytes(h, w);
+    return NSM_OK;
+}
+
+static CamParams cam_params(const nsm_frame_params* fp) {
+    CamParams c;
+    for (int k = 0; k < 16; ++k) c.m[k] = fp->m_cam[k];
+    for (int k = 0; k < 3; ++k) {
+        c.E[k] = fp->cam_pos[k];
+        c.fwd[k] = fp->cam_fwd[k];
+        c.right[k] = fp->cam_right[k];
+        c.up[k] = fp->cam_up[k];
+    }
+    c.tanx = fp->cam_tan_half_x;
+    c.tany = fp->cam_tan_half_y;
+    return c;
+}
+
+nsm_status nsm_temporal_instability(const float* tris, const float* tri_normals, int n_tris,
+                                    const nsm_frame_params* prev, const nsm_frame_params* cur,
+                                    const uint64_t* gbuf_prev, const uint64_t* gbuf_cur,
+                                    const float* vis_prev, const float* vis_cur, int h, int w, float alpha,
+                                    float depth_tol, float cos_tol, int accumulate, double* acc_out,
+                                    float* d_out, void* workspace, size_t ws_bytes, void* stream) {
+    if (!prev || !cur || !gbuf_prev || !gbuf_cur || !vis_prev || !vis_cur || !acc_out || n_tris < 0)
+        return NSM_E_INVALID_ARG;
+    if (n_tris > 0 && (!tris || !tri_normals)) return NSM_E_INVALID_ARG;
+    if (h < 1 || w < 1 || h > kMaxImage || w > kMaxImage) return NSM_E_SHAPE;
+    if (!workspace || ws_bytes < temporal_workspace_bytes(h, w)) return NSM_E_WORKSPACE;
+    if (!device_ok()) return NSM_E_DEVICE;
+    if (temporal_pair(tris, tri_normals, n_tris, cam_params(prev), cam_params(cur), gbuf_prev, gbuf_cur,
+                      vis_prev, vis_cur, h, w, alpha, depth_tol, cos_tol, accumulate, acc_out, d_out,
+                      workspace, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+        return NSM_E_LAUNCH;
+    return NSM_OK;
+}
+
 }  // extern "C"

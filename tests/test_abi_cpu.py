@@ -131,3 +131,52 @@ def test_features_validation():
     with pytest.raises(nsm.NsmError) as e:
         nsm.nsm_build_features(**{**args, "fs": 5})
     assert e.value.status == 1
+
+
+def test_s2d_network_plan():
+    from oracle import paper_net as pn
+    for widths in ((16, 32, 64), (16, 32, 64, 128, 256)):
+        ctx = nsm.nsm_create(4, widths, "bf16", "paper_s2d")
+        assert nsm.nsm_param_count(ctx) == pn.n_params(4, widths, s2d=True)
+        with pytest.raises(nsm.NsmError) as e:
+            m = 1 << (len(widths) - 1)            # sizes must be multiples of 2^(L-1)
+            nsm.nsm_workspace_bytes(ctx, 1, 3 * m + 2, 4 * m, training=0)
+        assert e.value.status == 2
+        nsm.nsm_destroy(ctx)
+
+
+def test_temporal_validation():
+    import nsm_synth as S
+    need = nsm.nsm_perturbation_loss_workspace_bytes(2, 3, 64, 96)
+    assert need >= 8 * ((2 * 64 * 96 + 255) // 256)
+    for bad in ((0, 3, 64, 96), (2, 17, 64, 96), (2, -1, 64, 96), (2, 3, 0, 96), (2, 3, 64, 16385)):
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_perturbation_loss_workspace_bytes(*bad)
+        assert e.value.status == 2
+    args = dict(vis=1024, target=2048, n=2, p=3, h=64, w=96, alpha=0.9, loss_out=4096, dvis0_out=8192,
+                workspace=16384, ws_bytes=need, stream=0)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_perturbation_loss(**{**args, "ws_bytes": need - 1})
+    assert e.value.status == 4
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_perturbation_loss(**{**args, "dvis0_out": None})
+    assert e.value.status == 1
+    sc, fr = S.workload_frame("tiny_64", 0)
+    tneed = nsm.nsm_temporal_workspace_bytes(64, 64)
+    assert tneed >= 16 * (64 * 64 // 256)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_temporal_workspace_bytes(64, 0)
+    assert e.value.status == 2
+    targs = dict(tris=1024, tri_normals=2048, n_tris=sc.n_tris, fp_prev=fr, fp_cur=fr, gbuf_prev=4096,
+                 gbuf_cur=8192, vis_prev=12288, vis_cur=16384, h=64, w=64, alpha=3.0, depth_tol=0.01,
+                 cos_tol=0.9, accumulate=1, acc_out=20480, d_out=None, workspace=24576, ws_bytes=tneed,
+                 stream=0)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_temporal_instability(**{**targs, "ws_bytes": tneed - 1})
+    assert e.value.status == 4
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_temporal_instability(**{**targs, "acc_out": None})
+    assert e.value.status == 1
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_temporal_instability(**{**targs, "h": 16385})
+    assert e.value.status == 2
