@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms/frame 1080p shadow-net inference, BF16 vs FP32, at stated visibility error"
 HBM_PEAK = 8.0e12                         # B/s
-MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}   # dense FLOP/s
+MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15,
+             "f8": 2.5e15}   # dense FLOP/s; the 8-bit storage form computes on bf16 MFMA
 WORKLOAD = "hard_1080p"
 CALIB_COPY_BYTES = 256 << 20
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "hbm_traffic_1080p_bf16.md")
@@ -52,7 +53,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", default="frame", choices=["frame", "none"])
-    ap.add_argument("--forms", default="bf16,f32,f16")
+    ap.add_argument("--forms", default="bf16,f32,f16,f8")
     ap.add_argument("--batched", type=int, default=1, help="also time the 16-frame graph batch")
     ap.add_argument("--paper-net", type=int, default=1, help="also time the paper's 5-level net")
     ap.add_argument("--training", type=int, default=1, help="also time the 32-frame FP32 training step")
@@ -65,8 +66,10 @@ def parse():
 
 def stage_costs(widths, c_in, h, w, dtype):
     """Algorithmic FLOPs and HBM bytes per frame of each conv stage (fused:
-    every tensor written once and read once per consumer; weights included)."""
-    es = 4 if dtype == "f32" else 2
+    every tensor written once and read once per consumer; weights included).
+    Activations take 4, 2 or (8-bit storage) 1 byte; weights 4 or 2."""
+    es = {"f32": 4, "f8": 1}.get(dtype, 2)
+    ws = 4 if dtype == "f32" else 2
     w0, w1, w2 = widths
     L1, L2 = (h // 2) * (w // 2), (h // 4) * (w // 4)
     L0 = h * w
@@ -74,7 +77,7 @@ def stage_costs(widths, c_in, h, w, dtype):
 
     def add(key, px, cs, cu, co, in_bytes, out_bytes):
         flops = 2.0 * px * co * 9 * (cs + cu)
-        wbytes = co * 9 * (cs + cu) * es + co * 4
+        wbytes = co * 9 * (cs + cu) * ws + co * 4
         out[key] = (flops, in_bytes + out_bytes + wbytes)
 
     add(f"conv3x3 {c_in}+0->{w0} Pool", L0, c_in, 0, w0, L0 * c_in * 4, L0 * w0 * es + L1 * w0 * es)
@@ -95,7 +98,7 @@ def stage_costs(widths, c_in, h, w, dtype):
 def _base(name):
     """Traced kernel name without its trailing storage-type suffix."""
     head, _, last = name.rpartition(" ")
-    return head if last in ("bf16", "f16", "f32") else name
+    return head if last in ("bf16", "f16", "f32", "f8") else name
 
 
 def raster_costs(n_tris, h, w, sm):

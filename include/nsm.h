@@ -55,7 +55,7 @@ typedef enum {
     NSM_E_LAUNCH = 7        /* a kernel launch was rejected                      */
 } nsm_status;
 
-typedef enum { NSM_F32 = 0, NSM_BF16 = 1, NSM_F16 = 2 } nsm_dtype;
+typedef enum { NSM_F32 = 0, NSM_BF16 = 1, NSM_F16 = 2, NSM_F8 = 3 } nsm_dtype;
 
 /* Feature sets (channel order, NHWC, float32):
  *   HARD6:  [d/f_C, n.x, n.y, n.z, (z - z_f)/f_L, z/f_L]
@@ -177,7 +177,14 @@ nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n
  * stay float32.  Decoder stages fold the bilinear x2 upsampling into their
  * weights away from the image border (four phase kernels per stage, formed
  * in float64 and rounded once to the storage type), so the upsampled tensor
- * is never rounded to the storage type there. */
+ * is never rounded to the storage type there.
+ * NSM_F8 is 8-bit temporary storage (suggested as future work in the
+ * paper's supplemental Sec. 3 and Sec. 8): activations between stages are
+ * stored as FP8 E4M3 (OCP: bias 7, 3 mantissa bits, saturated to +-448,
+ * rounded to nearest even), widened to bfloat16 when staged, and computed
+ * with bfloat16 weights on bfloat16 MFMA; it halves the activation bytes of
+ * NSM_BF16 at E4M3's precision (relative step 1/8).  NSM_ARCH_UNET only
+ * (NSM_E_UNSUPPORTED otherwise). */
 nsm_status nsm_create(const nsm_net_desc *desc, nsm_dtype dtype, nsm_ctx **out);
 nsm_status nsm_destroy(nsm_ctx *ctx);
 

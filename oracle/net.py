@@ -30,7 +30,8 @@ Low-precision emulation: the same forward with round-to-nearest-even to the
 storage type (bfloat16 or float16) applied exactly where the GPU stores a
 value in that type (features on load, 3x3 weights, every stored activation
 and the upsampled operand), accumulating in float64.  The 1x1 head keeps
-float32 weights and reads the unrounded last activation.
+float32 weights and reads the unrounded last activation.  The 8-bit storage
+form rounds stored activations to FP8 E4M3 and the rest to bfloat16.
 """
 import numpy as np
 
@@ -253,9 +254,27 @@ def round_f16(x):
     return np.asarray(x, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
 
 
+def round_e4m3(x):
+    """Round to the nearest OCP FP8 E4M3 value (ties to even), saturating at
+    +-448: 4 exponent bits with bias 7 and 3 mantissa bits, so normal values
+    step by 2^(e-3) in the binade [2^e, 2^(e+1)), e = -6 .. 8, and the
+    subnormals below 2^-6 are multiples of 2^-9."""
+    x = np.asarray(x, np.float64)
+    a = np.minimum(np.abs(x), 448.0)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -6)))
+    step = np.exp2(e - 3)
+    q = np.minimum(np.round(a / step) * step, 448.0)      # np.round: half to even
+    return np.where(x < 0, -q, q)
+
+
 def forward_lowp(c_in, widths, flat, feat, dtype):
-    """Forward with storage rounding emulated at the GPU's store points."""
-    rnd = {"bf16": round_bf16, "f16": round_f16}[dtype]
+    """Forward with storage rounding emulated at the GPU's store points.
+
+    dtype 'f8' is 8-bit temporary storage: activations are stored as E4M3,
+    while features on load, weights and the upsampled operand are bfloat16
+    (the compute type)."""
+    rnd = {"bf16": round_bf16, "f16": round_f16, "f8": round_bf16}[dtype]
+    st = round_e4m3 if dtype == "f8" else rnd
     P = split_params(c_in, widths, flat)
     Pq = {k: (rnd(w), b) for k, (w, b) in P.items()}
     Pq["H"] = P["H"]
@@ -267,13 +286,13 @@ def forward_lowp(c_in, widths, flat, feat, dtype):
     skips = []
     for l in range(L - 1):
         a = relu(conv3x3(cur, *Pq[f"E{l}"]))
-        skips.append(rnd(a))
-        cur = rnd(maxpool2(a))
-    cur = rnd(relu(conv3x3(cur, *Pq["B"])))
+        skips.append(st(a))
+        cur = st(maxpool2(a))
+    cur = st(relu(conv3x3(cur, *Pq["B"])))
     for l in range(L - 2, -1, -1):
         u = rnd(upsample2(cur))
         a = relu(conv3x3(np.concatenate([skips[l], u], axis=-1), *Pq[f"D{l}"]))
-        cur = a if l == 0 else rnd(a)
+        cur = a if l == 0 else st(a)
     wh, bh = Pq["H"]
     logits = cur @ wh[0, 0, 0, :] + bh[0]
     return {"logits": logits, "vis": sigmoid(logits)}

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, "libnsm.so")
 NSM_OK = 0
 STATUS_NAMES = {0: "NSM_OK", 1: "NSM_E_INVALID_ARG", 2: "NSM_E_SHAPE", 3: "NSM_E_UNSUPPORTED",
                 4: "NSM_E_WORKSPACE", 5: "NSM_E_NO_WEIGHTS", 6: "NSM_E_DEVICE", 7: "NSM_E_LAUNCH"}
-DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "f8": 3}
 FEATURE_SETS = {"hard6": 0, "soft8": 1, "paper4": 2}
 FEATURE_CHANNELS = {"hard6": 6, "soft8": 8, "paper4": 4}
 ARCHS = {"unet": 0, "paper": 1, "paper_s2d": 2}

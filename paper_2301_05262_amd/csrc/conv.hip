@@ -23,7 +23,10 @@ using namespace ck;
     X(8, 16, 8, Head, false, 8)
 
 template <Dt D> constexpr const char* dt_suffix() {
-    return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : " f16");
+    return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : (D == Dt::F16 ? " f16" : " f8"));
+}
+template <Dt D> constexpr const char* phase_suffix() {
+    return D == Dt::F32 ? " phase f32" : (D == Dt::BF16 ? " phase bf16" : (D == Dt::F16 ? " phase f16" : " phase f8"));
 }
 
 // Tile rows of the phase-form kernel: 16, or 8 where float32 tiles of wide
@@ -46,7 +49,7 @@ hipError_t launch_stage(const ConvArgs& a, hipStream_t s, const char* name) {
         constexpr int THU = up_tile_rows<D, CS, CU>();
         const int gxt = (a.w + kTW - 1) / kTW, gyt = (a.h + THU - 1) / THU;
         if (gxt >= 3 && gyt >= 3) {
-            TraceScope ts(name, D == Dt::F32 ? " phase f32" : (D == Dt::BF16 ? " phase bf16" : " phase f16"), s);
+            TraceScope ts(name, phase_suffix<D>(), s);
             const void* wup = reinterpret_cast<const char*>(a.wpk) + align256c(packed_bytes<D, CS, CU, CO>());
             const int blocks = border_tiles_per_image(THU, TH, a.h, a.w) * a.n + (gxt - 2) * (gyt - 2) * a.n;
             k_conv3x3_up<D, CS, CU, CO, MODE, THU, TH><<<blocks, kThreads, 0, s>>>(a, wup);
@@ -118,6 +121,8 @@ size_t packed_weight_bytes(const ConvStage& st, Dt dt) {
         case Dt::F32: ok = pack_dispatch<Dt::F32>(st, nullptr, nullptr, nullptr, &b); break;
         case Dt::BF16: ok = pack_dispatch<Dt::BF16>(st, nullptr, nullptr, nullptr, &b); break;
         case Dt::F16: ok = pack_dispatch<Dt::F16>(st, nullptr, nullptr, nullptr, &b); break;
+        // the 8-bit storage form keeps bfloat16 weights: the same pack
+        case Dt::F8: ok = pack_dispatch<Dt::BF16>(st, nullptr, nullptr, nullptr, &b); break;
     }
     return ok ? b : 0;
 }
@@ -128,6 +133,7 @@ hipError_t pack_weights(const ConvStage& st, Dt dt, const float* w_ohwi, void* p
         case Dt::F32: ok = pack_dispatch<Dt::F32>(st, w_ohwi, packed, s, nullptr); break;
         case Dt::BF16: ok = pack_dispatch<Dt::BF16>(st, w_ohwi, packed, s, nullptr); break;
         case Dt::F16: ok = pack_dispatch<Dt::F16>(st, w_ohwi, packed, s, nullptr); break;
+        case Dt::F8: ok = pack_dispatch<Dt::BF16>(st, w_ohwi, packed, s, nullptr); break;
     }
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -139,6 +145,7 @@ hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs
         case Dt::F32: e = launch<Dt::F32>(st, mode, a, s, &found); break;
         case Dt::BF16: e = launch<Dt::BF16>(st, mode, a, s, &found); break;
         case Dt::F16: e = launch<Dt::F16>(st, mode, a, s, &found); break;
+        case Dt::F8: e = launch<Dt::F8>(st, mode, a, s, &found); break;
     }
     return found ? e : hipErrorInvalidValue;
 }

@@ -45,6 +45,19 @@ template <Dt D> struct DT;
 template <> struct DT<Dt::F32> { using T = float; static constexpr int EPB = 4; };
 template <> struct DT<Dt::BF16> { using T = __bf16; static constexpr int EPB = 8; };
 template <> struct DT<Dt::F16> { using T = _Float16; static constexpr int EPB = 8; };
+// 8-bit temporary storage: bfloat16 in LDS and in the MFMAs, FP8 E4M3 in
+// global memory (ST below).
+template <> struct DT<Dt::F8> { using T = __bf16; static constexpr int EPB = 8; };
+
+// One FP8 E4M3 (OCP: bias 7, 3 mantissa bits, max 448, no infinities) value.
+struct e4m3 {
+    unsigned char bits;
+};
+
+// Storage type of activations in global memory: the compute type, except
+// for the 8-bit storage form.
+template <Dt D> struct ST { using S = typename DT<D>::T; };
+template <> struct ST<Dt::F8> { using S = e4m3; };
 
 constexpr int kThreads = 256;
 constexpr int kTW = 32;   // tile width: two 16-pixel MFMA column fragments
@@ -84,6 +97,34 @@ template <> __device__ __forceinline__ float from_f<float>(float v) { return v; 
 template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float v) { return (__bf16)v; }
 template <> __device__ __forceinline__ _Float16 from_f<_Float16>(float v) { return (_Float16)v; }
 
+// float -> E4M3: saturate to +-448, then the hardware conversion (round to
+// nearest, ties to even).
+template <> __device__ __forceinline__ e4m3 from_f<e4m3>(float v) {
+    const float c = __builtin_amdgcn_fmed3f(v, 448.0f, -448.0f);
+    return e4m3{(unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(c, c, 0, false) & 0xFF)};
+}
+
+// Four floats -> four E4M3 bytes (v[0] in the lowest byte).
+__device__ __forceinline__ unsigned int pack4_e4m3(const float* v) {
+    float c[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) c[e] = __builtin_amdgcn_fmed3f(v[e], 448.0f, -448.0f);
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], w, true);
+    return (unsigned int)w;
+}
+
+// Eight E4M3 bytes -> eight bfloat16 (exact: every E4M3 value is a bfloat16).
+__device__ __forceinline__ u32x4 widen8_e4m3(unsigned int lo, unsigned int hi) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, false);
+    const bf16x2 b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, true);
+    const bf16x2 c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, false);
+    const bf16x2 d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, true);
+    return u32x4{__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b),
+                 __builtin_bit_cast(unsigned int, c), __builtin_bit_cast(unsigned int, d)};
+}
+
 template <Dt D>
 __device__ __forceinline__ f32x4 mfma_kgroup(const u32x4& wa, const u32x4& xb, f32x4 acc) {
     if constexpr (D == Dt::F32) {
@@ -93,7 +134,7 @@ __device__ __forceinline__ f32x4 mfma_kgroup(const u32x4& wa, const u32x4& xb, f
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
-    } else if constexpr (D == Dt::BF16) {
+    } else if constexpr (D == Dt::BF16 || D == Dt::F8) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, wa),
                                                       __builtin_bit_cast(bf16x8, xb), acc, 0, 0, 0);
     } else {
@@ -138,6 +179,22 @@ __device__ __forceinline__ u32x4 buf_load16(__amdgpu_buffer_rsrc_t r, int voff, 
     return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
 }
 
+// One block of EPB activations at byte offset voff of a storage-type tensor,
+// as EPB compute-type values (16 bytes): a 16-byte load, or for the 8-bit
+// storage form an 8-byte load widened to bfloat16.
+template <Dt D>
+__device__ __forceinline__ u32x4 load_blk(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (D == Dt::F8) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        return widen8_e4m3(q[0], q[1]);
+    } else {
+        return buf_load16(r, voff, soff);
+    }
+}
+// Bytes of one block in global memory.
+template <Dt D> constexpr int blk_bytes() { return DT<D>::EPB * (int)sizeof(typename ST<D>::S); }
+
 // Four consecutive channels (converted to T) as one 8- or 16-byte buffer store.
 template <typename T>
 __device__ __forceinline__ void buf_store4(__amdgpu_buffer_rsrc_t r, int voff, int soff, const f32x4& v) {
@@ -148,6 +205,9 @@ __device__ __forceinline__ void buf_store4(__amdgpu_buffer_rsrc_t r, int voff, i
         u32x4 q;
         __builtin_memcpy(&q, t4, 16);
         __builtin_amdgcn_raw_buffer_store_b128(q, r, voff, soff, 0);
+    } else if constexpr (sizeof(T) == 1) {
+        const float f4[4] = {v[0], v[1], v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b32(pack4_e4m3(f4), r, voff, soff, 0);
     } else {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
         u32x2 q;
@@ -315,7 +375,9 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     // phase 1: same-resolution channels, and the low-res source rows.
     // Buffer offsets are relative to each tile's first (halo) pixel, taken
     // at clamped coordinates; pixels outside the image then read as zero.
-    constexpr int SZ_IN = IN_F32 ? 4 : (int)sizeof(T);
+    using S = typename ST<D>::S;
+    constexpr int SB = (int)sizeof(S);                              // bytes per stored element
+    constexpr int SZ_IN = IN_F32 ? 4 : SB;
     constexpr int SPX = S2D ? 2 * (CS / 4) * 4 : CS * SZ_IN;          // bytes per pixel step
     const int srow = S2D ? 2 * (2 * w) * (CS / 4) * 4 : w * CS * SZ_IN;  // bytes per row step
     const char* sbase = reinterpret_cast<const char*>(in) + ((long long)n * h + y0 - 1) * srow +
@@ -361,7 +423,7 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
             }
             v = pack_block<D>(f);
         } else {
-            v = buf_load16(sr, voff + ch * 16, 0);
+            v = load_blk<D>(sr, voff + ch * blk_bytes<D>(), 0);
         }
         return ok ? v : u32x4{0u, 0u, 0u, 0u};
     };
@@ -372,13 +434,13 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     const int hl = h >> 1, wl = w >> 1;
     const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
     const char* lbase = reinterpret_cast<const char*>(low) +
-                        ((((long long)n * hl + ly0) * wl + lx0) * CU) * (long long)sizeof(T);
+                        ((((long long)n * hl + ly0) * wl + lx0) * CU) * (long long)SB;
     const __amdgpu_buffer_rsrc_t lr = buf_rsrc(lbase);
-    const int lrow = wl * CU * (int)sizeof(T);
+    const int lrow = wl * CU * SB;
     auto low_ld = [&](int r, int k) -> u32x4 {
         const int c = k / (NCH_U > 0 ? NCH_U : 1), ch = k - c * NCH_U;
         const int gy = min(max(ly0 + r, 0), hl - 1) - ly0, gx = min(max(lx0 + c, 0), wl - 1) - lx0;
-        return buf_load16(lr, gy * lrow + gx * (CU * (int)sizeof(T)) + ch * 16, 0);
+        return load_blk<D>(lr, gy * lrow + gx * (CU * SB) + ch * blk_bytes<D>(), 0);
     };
     auto low_st = [&](int r, int k, const u32x4& v) {
         const int c = k / (NCH_U > 0 ? NCH_U : 1), ch = k - c * NCH_U;
@@ -479,6 +541,8 @@ __device__ __forceinline__ void store4(T* dst, int co, const float* v) {
         f32x4 q;
         __builtin_memcpy(&q, t4, 16);
         *reinterpret_cast<f32x4*>(dst) = q;
+    } else if constexpr (sizeof(T) == 1) {
+        *reinterpret_cast<unsigned int*>(dst) = pack4_e4m3(v);
     } else {
         uint2 q;
         __builtin_memcpy(&q, t4, 8);
@@ -604,7 +668,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
             }
         }
     } else {
-        T* out = reinterpret_cast<T*>(a.out);
+        using S = typename ST<D>::S;
+        S* out = reinterpret_cast<S*>(a.out);
 #pragma unroll
         for (int m = 0; m < MF; ++m) {
             const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
@@ -615,13 +680,13 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
                     const int co = f * 16 + 4 * g;
                     if (co < CO) {
                         float v4[4] = {acc[m][f][0], acc[m][f][1], acc[m][f][2], acc[m][f][3]};
-                        store4<T, CO>(out + p * CO + co, co, v4);
+                        store4<S, CO>(out + p * CO + co, co, v4);
                     }
                 }
             }
         }
         if constexpr (MODE == OutMode::Pool) {
-            T* pooled = reinterpret_cast<T*>(a.pooled);
+            S* pooled = reinterpret_cast<S*>(a.pooled);
             const int hp = h >> 1, wp = w >> 1;
             // row pair pr of this wave = fragments 4 pr + cf (upper row) and 4 pr + 2 + cf
 #pragma unroll
@@ -640,7 +705,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
                     const int co = f * 16 + 4 * g;
                     if ((px & 1) == 0 && yp < hp && xp < wp && co < CO) {
                         const size_t p = ((size_t)n * hp + yp) * wp + xp;
-                        store4<T, CO>(pooled + p * CO + co, co, mx);
+                        store4<S, CO>(pooled + p * CO + co, co, mx);
                     }
                 }
             }

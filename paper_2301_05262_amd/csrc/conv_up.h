@@ -162,18 +162,19 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     // columns x0-1 .. x0+32, low rows y0/2-1 .. y0/2+TH/2 and columns
     // x0/2-1 .. x0/2+16, all inside the image (and no clamping is needed).
     {
-        using TT = typename DT<D>::T;
-        constexpr int KS = 34 * G::BPT_S, KL = UT::LC * G::BPT_U;   // 16-byte chunks per tile row
-        const TT* sbase = reinterpret_cast<const TT*>(a.in) + (((size_t)n * h + y0 - 1) * w + x0 - 1) * CS;
-        const TT* lbase = reinterpret_cast<const TT*>(a.low) + (((size_t)n * hl + (y0 >> 1) - 1) * wl + (x0 >> 1) - 1) * CU;
+        using S = typename ST<D>::S;
+        constexpr int KS = 34 * G::BPT_S, KL = UT::LC * G::BPT_U;   // blocks per tile row
+        constexpr int BB = blk_bytes<D>();
+        const S* sbase = reinterpret_cast<const S*>(a.in) + (((size_t)n * h + y0 - 1) * w + x0 - 1) * CS;
+        const S* lbase = reinterpret_cast<const S*>(a.low) + (((size_t)n * hl + (y0 >> 1) - 1) * wl + (x0 >> 1) - 1) * CU;
         const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase), lr = buf_rsrc(lbase);
-        const int srow = w * CS * (int)sizeof(TT), lrow = wl * CU * (int)sizeof(TT);
-        auto skip_ld = [&](int r, int k) -> u32x4 { return buf_load16(sr, r * srow + k * 16, 0); };
+        const int srow = w * CS * (int)sizeof(S), lrow = wl * CU * (int)sizeof(S);
+        auto skip_ld = [&](int r, int k) -> u32x4 { return load_blk<D>(sr, r * srow + k * BB, 0); };
         auto skip_st = [&](int r, int k, const u32x4& v) {
             const int c = k / G::BPT_S, cb = k - c * G::BPT_S;
             *reinterpret_cast<u32x4*>(&skip[((r * 2 + (c & 1)) * UT::SC + (c >> 1)) * CSTS + cb * EPB]) = v;
         };
-        auto low_ld = [&](int r, int k) -> u32x4 { return buf_load16(lr, r * lrow + k * 16, 0); };
+        auto low_ld = [&](int r, int k) -> u32x4 { return load_blk<D>(lr, r * lrow + k * BB, 0); };
         auto low_st = [&](int r, int k, const u32x4& v) {
             const int c = k / G::BPT_U, cb = k - c * G::BPT_U;
             *reinterpret_cast<u32x4*>(&lowt[(r * UT::LC + c) * CSTU + cb * EPB]) = v;
@@ -324,9 +325,10 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
         // interior tile: every pixel is in the image; offsets relative to the
         // tile's first pixel, the row step in a scalar register
         static_assert(CO % 16 == 0, "stored decoder stages fill whole 16-channel fragments");
-        constexpr int SZ = (int)sizeof(T);
+        using S = typename ST<D>::S;
+        constexpr int SZ = (int)sizeof(S);
         const __amdgpu_buffer_rsrc_t orc =
-            buf_rsrc(reinterpret_cast<T*>(a.out) + (((size_t)n * h + y0) * w + x0) * CO);
+            buf_rsrc(reinterpret_cast<S*>(a.out) + (((size_t)n * h + y0) * w + x0) * CO);
         const int voff = (((py + 2 * RW * half) * w + 2 * j) * CO + 4 * g) * SZ;
         const int rstep = 2 * w * CO * SZ;
 #pragma unroll
@@ -335,7 +337,7 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
             for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
-                    buf_store4<T>(orc, voff, m * rstep + (p * CO + f * 16) * SZ, acc[m][p][f]);
+                    buf_store4<S>(orc, voff, m * rstep + (p * CO + f * 16) * SZ, acc[m][p][f]);
     }
 }
 

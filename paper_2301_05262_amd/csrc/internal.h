@@ -85,7 +85,9 @@ hipError_t temporal_pair(const float* tris, const float* normals, int n_tris, co
                          int accumulate, double* acc_out, float* d_out, void* ws, hipStream_t s);
 
 // --------------------------------------------------------------- network
-enum class Dt { F32 = 0, BF16 = 1, F16 = 2 };
+// F8: 8-bit temporary storage -- activations stored in global memory as FP8
+// E4M3 (OCP), weights and compute in bfloat16.
+enum class Dt { F32 = 0, BF16 = 1, F16 = 2, F8 = 3 };
 
 // One 3x3 conv stage as the kernels see it.
 struct ConvStage {

@@ -145,10 +145,11 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
 nsm_status nsm_create(const nsm_net_desc* desc, nsm_dtype dtype, nsm_ctx** out) {
     if (!desc || !out) return NSM_E_INVALID_ARG;
     *out = nullptr;
-    if (dtype != NSM_F32 && dtype != NSM_BF16 && dtype != NSM_F16) return NSM_E_INVALID_ARG;
+    if (dtype != NSM_F32 && dtype != NSM_BF16 && dtype != NSM_F16 && dtype != NSM_F8) return NSM_E_INVALID_ARG;
     const int L = desc->levels;
     if (L < 2 || L > 5 || desc->c_in < 1) return NSM_E_UNSUPPORTED;
     if (desc->arch == NSM_ARCH_UNET && L > 4) return NSM_E_UNSUPPORTED;
+    if (desc->arch != NSM_ARCH_UNET && dtype == NSM_F8) return NSM_E_UNSUPPORTED;   // 8-bit storage: U-Net only
     for (int l = 0; l < L; ++l)
         if (desc->widths[l] < 1) return NSM_E_UNSUPPORTED;
     if (desc->arch != NSM_ARCH_UNET && desc->arch != NSM_ARCH_PAPER && desc->arch != NSM_ARCH_PAPER_S2D)
@@ -315,7 +316,8 @@ struct FwdLayout {
     size_t skip[4], pool[4], bott, dec[4], d0act, head4, total;
 };
 
-size_t elem_size(Dt dt) { return dt == Dt::F32 ? 4 : 2; }
+// bytes of one stored activation
+size_t elem_size(Dt dt) { return dt == Dt::F32 ? 4 : (dt == Dt::F8 ? 1 : 2); }
 
 FwdLayout plan_forward(const nsm_ctx* c, int n, int h, int w, bool training) {
     FwdLayout L{};

@@ -34,7 +34,7 @@ __device__ __forceinline__ f32x4 mfma_1x1(const uint2& wa, const f32x4& act, f32
         return acc;   // float32 path handled per element by the caller
     } else {
         T b4[4] = {from_f<T>(act[0]), from_f<T>(act[1]), from_f<T>(act[2]), from_f<T>(act[3])};
-        if constexpr (D == Dt::BF16) {
+        if constexpr (D == Dt::BF16 || D == Dt::F8) {
             bf16x4 a, b;
             __builtin_memcpy(&a, &wa, 8);
             __builtin_memcpy(&b, b4, 8);
@@ -207,8 +207,9 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
             if (y < h && x < w) out4[(((size_t)n * h + y) * w + x) * 4 + g] = mine + hb;
         }
     } else {
+        using S = typename ST<D>::S;
         if constexpr (MODE != PMode::PoolOnly) {
-            T* out = reinterpret_cast<T*>(a.out);
+            S* out = reinterpret_cast<S*>(a.out);
 #pragma unroll
             for (int m = 0; m < MF; ++m) {
                 const int y = y0 + wave * RPW + (m >> 1), x = x0 + (m & 1) * 16 + px;
@@ -219,14 +220,14 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
                         const int co = f2 * 16 + 4 * g;
                         if (co < C2) {
                             float v4[4] = {acc2[m][f2][0], acc2[m][f2][1], acc2[m][f2][2], acc2[m][f2][3]};
-                            store4<T, C2>(out + p * C2 + co, co, v4);
+                            store4<S, C2>(out + p * C2 + co, co, v4);
                         }
                     }
                 }
             }
         }
         if constexpr (POOL) {
-            T* pooled = reinterpret_cast<T*>(a.pooled);
+            S* pooled = reinterpret_cast<S*>(a.pooled);
             const int hp = h >> 1, wp = w >> 1;
 #pragma unroll
             for (int cf = 0; cf < 2; ++cf) {
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
                     const int co = f2 * 16 + 4 * g;
                     if ((px & 1) == 0 && yp < hp && xp < wp && co < C2) {
                         const size_t p = ((size_t)n * hp + yp) * wp + xp;
-                        store4<T, C2>(pooled + p * C2 + co, co, av);
+                        store4<S, C2>(pooled + p * C2 + co, co, av);
                     }
                 }
             }
@@ -328,7 +329,7 @@ __global__ void k_pack1x1(const float* __restrict__ w, void* __restrict__ out) {
     X(0, 16, false, 16, 16, Head, false, 8, false)
 
 template <Dt D> constexpr const char* pdt_suffix() {
-    return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : " f16");
+    return D == Dt::F32 ? " f32" : (D == Dt::BF16 ? " bf16" : (D == Dt::F16 ? " f16" : " f8"));
 }
 
 #define NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)                                  \
@@ -390,6 +391,7 @@ size_t pconv_packed_bytes(const PStage& st, Dt dt) {
         case Dt::F32: ppack<Dt::F32>(st, nullptr, nullptr, nullptr, nullptr, &b); break;
         case Dt::BF16: ppack<Dt::BF16>(st, nullptr, nullptr, nullptr, nullptr, &b); break;
         case Dt::F16: ppack<Dt::F16>(st, nullptr, nullptr, nullptr, nullptr, &b); break;
+        default: break;     // no 8-bit storage form of this network
     }
     return b;
 }
@@ -401,6 +403,7 @@ hipError_t pconv_pack(const PStage& st, Dt dt, const float* w3, const float* w1,
         case Dt::F32: ok = ppack<Dt::F32>(st, w3, w1, packed, s, nullptr); break;
         case Dt::BF16: ok = ppack<Dt::BF16>(st, w3, w1, packed, s, nullptr); break;
         case Dt::F16: ok = ppack<Dt::F16>(st, w3, w1, packed, s, nullptr); break;
+        default: break;
     }
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -427,6 +430,7 @@ hipError_t pconv_forward(const PStage& st, Dt dt, const PConvArgs& a, hipStream_
         case Dt::F32: e = plaunch<Dt::F32>(st, a, s, &found); break;
         case Dt::BF16: e = plaunch<Dt::BF16>(st, a, s, &found); break;
         case Dt::F16: e = plaunch<Dt::F16>(st, a, s, &found); break;
+        default: break;
     }
     return found ? e : hipErrorInvalidValue;
 }

@@ -216,3 +216,31 @@ def test_lowp_forward_close_to_fp64():
     for dt, tol in (("bf16", 2e-2), ("f16", 3e-3)):
         v = net.forward_lowp(6, U3.widths, flat, feat, dt)["vis"]
         assert 0 < np.abs(v - ref).max() < tol
+
+
+def test_e4m3_rounding_matches_torch_cast():
+    """The 8-bit storage rounding against torch's float8_e4m3fn cast (ties to
+    even) on random values, every representable value and every midpoint
+    between neighbours; saturation at 448 beyond the cast's range."""
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    vals = np.unique(codes[np.isfinite(codes)])
+    mids = 0.5 * (vals[1:] + vals[:-1])
+    mag = np.exp(rnd((6000,), 23, np.log(1e-4), np.log(460.0)))
+    x = np.concatenate([vals, mids, mag, -mag, [0.0, 2.0 ** -10, 3 * 2.0 ** -10]])
+    x = x[np.abs(x) < 464.0].astype(np.float32).astype(np.float64)
+    want = torch.from_numpy(x).to(torch.float32).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(net.round_e4m3(x), want)
+    np.testing.assert_array_equal(net.round_e4m3(vals), vals)
+    np.testing.assert_array_equal(net.round_e4m3([464.0, 1e6, -1e30]), [448.0, 448.0, -448.0])
+
+
+def test_f8_storage_forward_error():
+    """8-bit storage keeps bfloat16 weights and compute; only stored
+    activations carry E4M3's 3-bit mantissa (relative step 1/8)."""
+    flat = he_weights(U3, 5)
+    feat = rnd((1, 32, 32, 6), 22).astype(np.float32)
+    ref = net.forward(6, U3.widths, flat, feat)["vis"]
+    v8 = net.forward_lowp(6, U3.widths, flat, feat, "f8")["vis"]
+    vb = net.forward_lowp(6, U3.widths, flat, feat, "bf16")["vis"]
+    e8, eb = np.abs(v8 - ref).max(), np.abs(vb - ref).max()
+    assert eb < e8 < 0.1
