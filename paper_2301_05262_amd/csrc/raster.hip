@@ -31,6 +31,7 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr int kScanThreads = 1024;
 constexpr int kGroup = 32;            // virtual triangles per group of the item -> triangle search
 constexpr int kRasterBlocks = 2048;   // 8192 waves: 32 per CU on 256 CUs, one resident round
+constexpr int kStep = 2;              // tile items evaluated together in the walk
 
 __device__ __forceinline__ void to_clip(const Mat4& M, float x, float y, float z, float c[4]) {
 #pragma unroll
@@ -72,19 +73,19 @@ __device__ __forceinline__ void fill2(FillJob a, FillJob b, size_t tid, size_t s
     }
 }
 
-// Per-triangle float64 coefficients of the coverage and depth arithmetic,
-// read with scalar loads by the raster loop.  Edge k (opposite vertex k, from
-// vertex a to vertex b) is E_k(px, py) = dx_k py - dy_k px + c_k with
-// dx_k = Xb - Xa, dy_k = Yb - Ya, c_k = dy_k Xa - dx_k Ya: all exact integers.
-struct alignas(16) TriCoef {
+// Per-triangle coefficients of the coverage and depth arithmetic, staged in
+// LDS by the raster loop.  Edge k (opposite vertex k, from vertex a to vertex
+// b) is E_k(px, py) = dx_k py - dy_k px + c_k with dx_k = Xb - Xa,
+// dy_k = Yb - Ya, c_k = dy_k Xa - dx_k Ya: all exact integers.  104 bytes,
+// so that the LDS slots of 64 records per wave allow 6 waves per SIMD.
+struct alignas(8) TriCoef {
     double dx[3], dy[3], c[3];
-    double z[3];          // vertex ndc depths (float32 values)
     double area;          // doubled area (> 0)
     double inv_area;      // 1 / area rounded to nearest
+    float z[3];           // vertex ndc depths
     int32_t incl;         // bit k: edge k owns the pixels exactly on it
-    int32_t pad[3];
 };
-static_assert(sizeof(TriCoef) == 128, "TriCoef must stay 128 bytes");
+static_assert(sizeof(TriCoef) == 104, "TriCoef must stay 104 bytes");
 
 __device__ __forceinline__ bool edge_owns(int64_t dx, int64_t dy) {
     return dy > 0 || (dy == 0 && dx < 0);
@@ -160,14 +161,13 @@ __device__ __forceinline__ int tri_setup_one(const float* __restrict__ tris, int
     setup[t] = s;
     TriCoef c;
     c.incl = 0;
-    c.pad[0] = c.pad[1] = c.pad[2] = 0;
     for (int k = 0; k < 3; ++k) {
         const int a = (k + 1) % 3, b = (k + 2) % 3;
         const int64_t dx = (int64_t)s.x[b] - s.x[a], dy = (int64_t)s.y[b] - s.y[a];
         c.dx[k] = (double)dx;
         c.dy[k] = (double)dy;
         c.c[k] = fma((double)dy, (double)s.x[a], -((double)dx * (double)s.y[a]));
-        c.z[k] = (double)s.z[k];
+        c.z[k] = s.z[k];
         if (edge_owns(dx, dy)) c.incl |= 1 << k;
     }
     c.area = (double)s.area;
@@ -299,39 +299,56 @@ __device__ __forceinline__ int find_tri(const long long* __restrict__ gbase, con
 
 __device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// One (triangle, 8x8 tile) item, one texel per lane.
-__device__ __forceinline__ void raster_item(const TriCoef& c, int vk, int tx, int ty, int lx, int ly, int n_tris,
-                                            int w0, int h0, int w1, int h1, bool k0, bool k1, void* o0,
-                                            void* o1) {
-    const bool pass = vk >= n_tris;
-    const int t = vk - (pass ? n_tris : 0);
-    const int rw = pass ? w1 : w0, rh = pass ? h1 : h0;
-    const int i = tx * 8 + lx, j = ty * 8 + ly;
-    if (i >= rw || j >= rh) return;
-    const double px = (double)(256 * i + 128), py = (double)(256 * j + 128);
+// One (triangle, 8x8 tile) item, one texel per lane: the texel's depth
+// candidate, evaluated without branches so that the walk can interleave the
+// dependent float64 chains of two items.  `ok` is false where the texel is
+// outside the target, not covered, or outside the depth range.
+struct Frag {
+    bool ok, pass;
+    uint32_t bits, t;
+    int i, j, rw;
+};
+
+__device__ __forceinline__ Frag raster_eval(const TriCoef& c, int vk, int tx, int ty, int lx, int ly, int n_tris,
+                                            int w0, int h0, int w1, int h1) {
+    Frag f;
+    f.pass = vk >= n_tris;
+    f.t = (uint32_t)(vk - (f.pass ? n_tris : 0));
+    f.rw = f.pass ? w1 : w0;
+    const int rh = f.pass ? h1 : h0;
+    f.i = tx * 8 + lx;
+    f.j = ty * 8 + ly;
+    const double px = (double)(256 * f.i + 128), py = (double)(256 * f.j + 128);
     const double e0 = fma(c.dx[0], py, fma(-c.dy[0], px, c.c[0]));
     const double e1 = fma(c.dx[1], py, fma(-c.dy[1], px, c.c[1]));
     const double e2 = fma(c.dx[2], py, fma(-c.dy[2], px, c.c[2]));
-    const int incl = c.incl;
-    const bool in0 = (e0 > 0.0) | ((e0 == 0.0) & ((incl & 1) != 0));
-    const bool in1 = (e1 > 0.0) | ((e1 == 0.0) & ((incl & 2) != 0));
-    const bool in2 = (e2 > 0.0) | ((e2 == 0.0) & ((incl & 4) != 0));
-    if (!(in0 & in1 & in2)) return;
-    double num = e0 * c.z[0];
-    num = num + e1 * c.z[1];
-    num = num + e2 * c.z[2];
+    // E_k is an integer, so the tie rule "E > 0, or E == 0 on an owned edge"
+    // is E > t_k with t_k = -1 on owned edges and 0 otherwise; the record is
+    // the same for the whole wave, so the thresholds live in scalar registers
+    const int incl = __builtin_amdgcn_readfirstlane(c.incl);
+    const double t0 = (incl & 1) ? -1.0 : 0.0, t1 = (incl & 2) ? -1.0 : 0.0, t2 = (incl & 4) ? -1.0 : 0.0;
+    const bool cov = (e0 > t0) & (e1 > t1) & (e2 > t2) & (f.i < f.rw) & (f.j < rh);
+    double num = e0 * (double)c.z[0];
+    num = num + e1 * (double)c.z[1];
+    num = num + e2 * (double)c.z[2];
     const double q0 = num * c.inv_area;
     const double q = fma(fma(-q0, c.area, num), c.inv_area, q0);
     const float d = (float)q;
-    if (!(d >= 0.0f && d <= 1.0f)) return;
+    f.ok = cov & (d >= 0.0f) & (d <= 1.0f);
     uint32_t bits = __float_as_uint(d);
     if ((bits & 0x7FFFFFFFu) == 0) bits = 0;  // -0 -> +0
-    const size_t o = (size_t)j * (size_t)rw + (size_t)i;
-    if (pass ? k1 : k0) {
-        const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)t;
-        atomicMin(reinterpret_cast<unsigned long long*>(pass ? o1 : o0) + o, key);
+    f.bits = bits;
+    return f;
+}
+
+__device__ __forceinline__ void raster_store(const Frag& f, bool k0, bool k1, void* o0, void* o1) {
+    if (!f.ok) return;
+    const size_t o = (size_t)f.j * (size_t)f.rw + (size_t)f.i;
+    if (f.pass ? k1 : k0) {
+        const unsigned long long key = ((unsigned long long)f.bits << 32) | (unsigned long long)f.t;
+        atomicMin(reinterpret_cast<unsigned long long*>(f.pass ? o1 : o0) + o, key);
     } else {
-        atomicMin(reinterpret_cast<uint32_t*>(pass ? o1 : o0) + o, bits);
+        atomicMin(reinterpret_cast<uint32_t*>(f.pass ? o1 : o0) + o, f.bits);
     }
 }
 
@@ -377,22 +394,40 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
             tx = setup[v].tx0 + local % ntx;
             ty = setup[v].ty0 + local / ntx;
         }
-        const int cnt = (int)min((long long)64, total - (chunk << 6));
+        const int cnt = __builtin_amdgcn_readfirstlane((int)min((long long)64, total - (chunk << 6)));
         // lane k stages its item's coefficient record in the wave's LDS slots
         // (64 vector loads in flight at once); the walk then reads each record
         // with same-address (broadcast) LDS reads instead of scalar loads
         {
-            const uint4* src = reinterpret_cast<const uint4*>(coef + v);
-            uint4* dst = reinterpret_cast<uint4*>(&lcoef[wv][lane]);
+            const uint2* src = reinterpret_cast<const uint2*>(coef + v);
+            uint2* dst = reinterpret_cast<uint2*>(&lcoef[wv][lane]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) dst[u] = src[u];
+            for (int u = 0; u < (int)(sizeof(TriCoef) / 8); ++u) dst[u] = src[u];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int k = 0; k < cnt; ++k) {
-            const int vk = bcast(v, k);
-            raster_item(lcoef[wv][k], vk, bcast(tx, k), bcast(ty, k), lx, ly, n_tris, w0, h0, w1, h1, k0, k1, o0, o1);
+        // kStep items per step: their records are read together and their
+        // independent float64 chains are all evaluated before the first store,
+        // so the chains overlap; items past the chunk's end repeat its last
+        // item (a repeated atomicMin changes nothing)
+        for (int k = 0; k < cnt; k += kStep) {
+            TriCoef cr[kStep];
+#pragma unroll
+            for (int u = 0; u < kStep; ++u) cr[u] = lcoef[wv][min(k + u, cnt - 1)];
+            Frag fr[kStep];
+#pragma unroll
+            for (int u = 0; u < kStep; ++u) {
+                const int ku = min(k + u, cnt - 1);
+                fr[u] = raster_eval(cr[u], bcast(v, ku), bcast(tx, ku), bcast(ty, ku), lx, ly, n_tris, w0, h0, w1,
+                                    h1);
+            }
+            // keep the evaluations above the stores (the compiler would otherwise
+            // sink each chain below the previous item's store branch)
+#pragma unroll
+            for (int u = 0; u < kStep; ++u) asm volatile("" ::"v"(fr[u].bits), "v"((int)fr[u].ok));
+#pragma unroll
+            for (int u = 0; u < kStep; ++u) raster_store(fr[u], k0, k1, o0, o1);
         }
         // the slots are rewritten for the next chunk only after every lane is done reading
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -12,8 +12,9 @@ traffic figures the benchmark reports.
       the same counter reads for the plain 256 MiB device copy that
       `bench.py --calib-copy 1` issues; ends with a machine-readable line
 
-The traffic figures are tied to the library sources they were measured on
-(a hash of csrc/): `recorded_traffic()` returns nothing once those differ.
+The traffic figures are tied to the library sources the profiled 1080p
+inference kernels are built from (rasteriser and gather, conv stages, their
+shared headers): `recorded_traffic()` returns nothing once those differ.
 """
 import csv
 import glob
@@ -28,13 +29,16 @@ CALIB_BYTES = 256 << 20          # the calibration copy: 256 MiB read, 256 MiB w
 TRAFFIC_TAG = "traffic-json:"
 
 
+# sources of the kernels the inference step launches
+PROFILED_SOURCES = ("raster.hip", "conv.hip", "conv_kernels.h", "conv_up.h", "internal.h")
+
+
 def source_hash():
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        if p.endswith((".hip", ".h")):
-            h.update(os.path.basename(p).encode())
-            with open(p, "rb") as f:
-                h.update(f.read())
+    for name in PROFILED_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
