@@ -29,10 +29,11 @@ template <Dt D> constexpr const char* phase_suffix() {
     return D == Dt::F32 ? " phase f32" : (D == Dt::BF16 ? " phase bf16" : (D == Dt::F16 ? " phase f16" : " phase f8"));
 }
 
-// Tile rows of the phase-form kernel: 16, or 8 where float32 tiles of wide
-// stages would leave room for only one block per CU.
+// Tile rows of the phase-form kernel: 16, or 8 for wide stages (96 input
+// channels), whose 16-row tiles hold 75 KB of LDS and 200+ registers per
+// lane in bfloat16 (two blocks per CU) and do not fit twice in float32.
 template <Dt D, int CS, int CU>
-constexpr int up_tile_rows() { return (D == Dt::F32 && CS + CU >= 96) ? 8 : 16; }
+constexpr int up_tile_rows() { return CS + CU >= 96 ? 8 : 16; }
 
 constexpr size_t align256c(size_t x) { return (x + 255) & ~(size_t)255; }
 
