@@ -255,7 +255,9 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
         const int n = (int)(t / ((long long)tiles_x * tiles_y));
         const int x0 = tx * kTW, y0 = ty * TH;
         __syncthreads();
-        load_halo_tile<Dt::F32, (CS % 4 != 0), CS, CU, CST, TH>(xt, lowt, a.in, a.low, n, a.h, a.w, x0, y0);
+        // pixel-major here (the wgrad walk indexes single channels of a pixel)
+        load_halo_tile<Dt::F32, (CS % 4 != 0), CS, CU, CST, DT<Dt::F32>::EPB, TH>(xt, lowt, a.in, a.low, n, a.h,
+                                                                                a.w, x0, y0);
         for (int idx = threadIdx.x; idx < TPX * (CO / 4); idx += 256) {
             const int px = idx / (CO / 4), c4 = idx - px * (CO / 4);
             const int y = y0 + px / kTW, x = x0 + (px % kTW);

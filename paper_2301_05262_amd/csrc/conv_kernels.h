@@ -75,6 +75,18 @@ __host__ __device__ constexpr int lds_stride(int cip) {
     return units * 16 / sz;
 }
 
+// LDS tiles of the conv kernels are block-major: one plane per 16-byte
+// channel block, pixel-consecutive inside the plane, planes a multiple of
+// 256 bytes (16 pixels) apart.  In the main loops the four 16-lane groups of
+// a wave read different blocks (or taps) of the same 16 pixels; measured on
+// gfx950, ds_read_b128 is conflict-free when the groups' planes are 256-byte
+// aligned apart, while a pixel-major layout (blocks of a pixel 16 bytes
+// apart) costs a second pass on every read.
+template <Dt D>
+__host__ __device__ constexpr int plane_stride(int npix) {
+    return (npix + 15) / 16 * 16 * DT<D>::EPB;
+}
+
 template <Dt D, int CS, int CU, int CO>
 struct Geo {
     static constexpr int EPB = DT<D>::EPB;
@@ -344,8 +356,9 @@ struct LowTile {
     static constexpr int SIZE = CU > 0 ? LH * LW * LCST : 1;
 };
 
-// Halo tile (TH+2) x (kTW+2) pixels of the stage input -> LDS, in the storage
-// dtype, CST elements per pixel: channels [0, CS) from `in` ([n][h][w][CS],
+// Halo tile (TH+2) x (kTW+2) pixels of the stage input -> LDS, in the
+// compute dtype, block b of pixel p at element p * PXS + b * BKS (block-major
+// planes: PXS = EPB, BKS = plane stride): channels [0, CS) from `in` ([n][h][w][CS],
 // float32 when IN_F32, zero-padded up to a whole block), channels
 // [CSP, CSP+CU) from the bilinear x2 upsampling of `low` ([n][h/2][w/2][CU]):
 // source row s = (y + 0.5)/2 - 0.5, taps floor(s) (weight 0.25 for even y,
@@ -360,7 +373,7 @@ struct LowTile {
 // through space-to-depth: channel (2 dy + dx) CS/4 + c of pixel (y, x) is
 // channel c of input pixel (2y + dy, 2x + dx), so every block of channels is
 // one contiguous run of an input row.
-template <Dt D, bool IN_F32, int CS, int CU, int CST, int TH, bool SUM = false, bool S2D = false>
+template <Dt D, bool IN_F32, int CS, int CU, int PXS, int BKS, int TH, bool SUM = false, bool S2D = false>
 __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename DT<D>::T* lowt,
                                                const void* in, const void* low, int n, int h, int w,
                                                int x0, int y0) {
@@ -384,7 +397,7 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
                         (long long)(x0 - 1) * SPX;
     const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase);
     auto skip_ld = [&](int r, int k) -> u32x4 {
-        const int c = k / (NCH_S > 0 ? NCH_S : 1), ch = k - c * NCH_S;
+        const int ch = k / WP, c = k - ch * WP;       // block-major: see the copy note below
         const int y = y0 + r - 1, x = x0 + c - 1;
         const bool ok = y >= 0 && y < h && x >= 0 && x < w;
         const int yr = min(max(y, 0), h - 1) - (y0 - 1), xr = min(max(x, 0), w - 1) - (x0 - 1);
@@ -428,8 +441,8 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
         return ok ? v : u32x4{0u, 0u, 0u, 0u};
     };
     auto skip_st = [&](int r, int k, const u32x4& v) {
-        const int c = k / (NCH_S > 0 ? NCH_S : 1), ch = k - c * NCH_S;
-        *reinterpret_cast<u32x4*>(&tile[(r * WP + c) * CST + ch * EPB]) = v;
+        const int ch = k / WP, c = k - ch * WP;       // block-major: see the copy note below
+        *reinterpret_cast<u32x4*>(&tile[(r * WP + c) * PXS + ch * BKS]) = v;
     };
     const int hl = h >> 1, wl = w >> 1;
     const int ly0 = (y0 >> 1) - 1, lx0 = (x0 >> 1) - 1;
@@ -438,14 +451,20 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     const __amdgpu_buffer_rsrc_t lr = buf_rsrc(lbase);
     const int lrow = wl * CU * SB;
     auto low_ld = [&](int r, int k) -> u32x4 {
-        const int c = k / (NCH_U > 0 ? NCH_U : 1), ch = k - c * NCH_U;
+        const int ch = k / LT::LW, c = k - ch * LT::LW;
         const int gy = min(max(ly0 + r, 0), hl - 1) - ly0, gx = min(max(lx0 + c, 0), wl - 1) - lx0;
         return load_blk<D>(lr, gy * lrow + gx * (CU * SB) + ch * blk_bytes<D>(), 0);
     };
     auto low_st = [&](int r, int k, const u32x4& v) {
-        const int c = k / (NCH_U > 0 ? NCH_U : 1), ch = k - c * NCH_U;
+        const int ch = k / LT::LW, c = k - ch * LT::LW;
         *reinterpret_cast<u32x4*>(&lowt[(r * LT::LW + c) * LT::LCST + ch * EPB]) = v;
     };
+    // Copy note: chunk k of a tile row is block ch = k / (pixels per row) of
+    // pixel c = k % (pixels per row), so that consecutive lanes store the same
+    // block of consecutive pixels: LDS addresses an odd number of 16-byte
+    // units apart, which never share a bank group (pixel-major chunks put the
+    // blocks of neighbouring pixels on the same banks).  The wave's loads
+    // still cover whole runs of pixels in global memory.
     if constexpr (NCH_S > 0 && CU > 0)
         copy_rows2<TH + 2, WP * NCH_S, LT::LH, LT::LW * NCH_U>(skip_ld, skip_st, low_ld, low_st, threadIdx.x);
     else if constexpr (NCH_S > 0)
@@ -454,9 +473,10 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
         copy_rows1<LT::LH, LT::LW * NCH_U>(low_ld, low_st, threadIdx.x);
     if constexpr (CU > 0) {
         __syncthreads();
-        // phase 2: upsampled channels from the staged rows
+        // phase 2: upsampled channels from the staged rows, pixel-fastest so
+        // that a wave writes consecutive pixels of one block
         for (int idx = threadIdx.x; idx < NPIX * NCH_U; idx += kThreads) {
-            const int pix = idx / NCH_U, ch = idx - pix * NCH_U;
+            const int ch = idx / NPIX, pix = idx - ch * NPIX;
             const int ty = pix / WP, tx = pix - ty * WP;
             const int y = y0 + ty - 1, x = x0 + tx - 1;
             u32x4 v = {0u, 0u, 0u, 0u};
@@ -475,13 +495,13 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
                     f[e] = wy0 * (wx0 * f00[e] + wx1 * f01[e]) + wy1 * (wx0 * f10[e] + wx1 * f11[e]);
                 if constexpr (SUM) {
                     float sk[EPB];
-                    unpack_block<D>(*reinterpret_cast<const u32x4*>(&tile[pix * CST + ch * EPB]), sk);
+                    unpack_block<D>(*reinterpret_cast<const u32x4*>(&tile[pix * PXS + ch * BKS]), sk);
 #pragma unroll
                     for (int e = 0; e < EPB; ++e) f[e] = sk[e] + f[e];
                 }
                 v = pack_block<D>(f);
             }
-            *reinterpret_cast<u32x4*>(&tile[pix * CST + (SUM ? 0 : CSP) + ch * EPB]) = v;
+            *reinterpret_cast<u32x4*>(&tile[pix * PXS + ((SUM ? 0 : NCH_S) + ch) * BKS]) = v;
         }
     }
     __syncthreads();
@@ -553,7 +573,8 @@ __device__ __forceinline__ void store4(T* dst, int co, const float* v) {
 // LDS elements of one tile of the general kernel (halo tile, then low rows).
 template <Dt D, int CS, int CU, int CO, int TH>
 struct GenTile {
-    static constexpr int TILE = (TH + 2) * (kTW + 2) * Geo<D, CS, CU, CO>::CST;
+    static constexpr int PS = plane_stride<D>((TH + 2) * (kTW + 2));
+    static constexpr int TILE = Geo<D, CS, CU, CO>::BPT * PS;
     static constexpr int LOW = LowTile<D, CU, TH>::SIZE;
     static constexpr int LOW_OFF = (TILE + 7) / 8 * 8;   // 16-byte aligned for every storage type
     static constexpr int ELEMS = LOW_OFF + LOW;
@@ -565,7 +586,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
                                           typename DT<D>::T* tile, typename DT<D>::T* lowt) {
     using T = typename DT<D>::T;
     using G = Geo<D, CS, CU, CO>;
-    constexpr int EPB = G::EPB, CST = G::CST, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
+    constexpr int EPB = G::EPB, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
+    constexpr int PS = GenTile<D, CS, CU, CO, TH>::PS;
     constexpr int WP = kTW + 2;
     constexpr int RPW = TH / 4;                 // rows per wave
     constexpr int MF = RPW * 2;                 // M-fragments per wave
@@ -573,7 +595,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
     const int h = a.h, w = a.w;
 
     // ---------------- prologue: halo tile to LDS
-    load_halo_tile<D, IN_F32, CS, CU, CST, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
+    load_halo_tile<D, IN_F32, CS, CU, EPB, PS, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     // ---------------- main loop
     // the wave index is uniform in the wave: keep it in a scalar register
@@ -604,11 +626,11 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
         if (b >= NB) b = NB - 1;               // padding k: weights are zero there
         const int tap = b / BPT, cb = b - tap * BPT;
         const int ky = tap / 3, kx = tap - ky * 3;
-        const int base = (ky * WP + kx + px) * CST + cb * EPB;
+        const int base = cb * PS + (ky * WP + kx + px) * EPB;
 #pragma unroll
         for (int m = 0; m < MF; ++m) {
             const int r = wave * RPW + (m >> 1), cf = m & 1;
-            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + (r * WP + cf * 16) * CST]);
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + (r * WP + cf * 16) * EPB]);
 #pragma unroll
             for (int f = 0; f < NF; ++f) acc[m][f] = mfma_kgroup<D>(wf[f], xb, acc[m][f]);
         }

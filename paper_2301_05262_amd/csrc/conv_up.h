@@ -29,7 +29,9 @@
 // w & 1 in half w >> 1 of the tile, TH/4 rows; each row is two 16-pixel MFMA
 // fragments, the even and the odd columns, so a fragment has one x-phase.
 // The skip tile is stored split by column parity, so that the 16 pixels of a
-// fragment (stride 2 in the image) are consecutive in LDS.
+// fragment (stride 2 in the image) are consecutive in LDS.  Both tiles are
+// block-major (one 256-byte aligned plane per 16-byte channel block), as in
+// the general kernel.
 #pragma once
 #include "conv_kernels.h"
 
@@ -60,7 +62,7 @@ struct UpGeo {
     static constexpr int NB_S = 9 * BPT_S, NB_U = 9 * BPT_U;
     static constexpr int NKG_S = (NB_S + 3) / 4, NKG_U = (NB_U + 3) / 4;
     static constexpr int NF = (CO + 15) / 16;
-    static constexpr int CSTS = lds_stride<D>(CS), CSTU = lds_stride<D>(CU);
+
     // packed weight elements: skip part, then 4 phases of the low-res part
     static constexpr size_t SKIP_ELEMS = (size_t)NF * NKG_S * 64 * EPB;
     static constexpr size_t PHASE_ELEMS = (size_t)NF * NKG_U * 64 * EPB;
@@ -72,8 +74,9 @@ template <Dt D, int CS, int CU, int TH>
 struct UpTile {
     static constexpr int SR = TH + 2, SC = 17;          // skip tile: rows x (2 parity planes x 17)
     static constexpr int LR = TH / 2 + 2, LC = kTW / 2 + 2;
-    static constexpr int SKIP = SR * 2 * SC * lds_stride<D>(CS);
-    static constexpr int LOW = LR * LC * lds_stride<D>(CU);
+    static constexpr int SPS = plane_stride<D>(SR * 2 * SC), LPS = plane_stride<D>(LR * LC);
+    static constexpr int SKIP = CS / DT<D>::EPB * SPS;
+    static constexpr int LOW = CU / DT<D>::EPB * LPS;
 };
 
 // Pack the phase-form weights from OHWI float32 W[CO][3][3][CS+CU]:
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     using G = UpGeo<D, CS, CU, CO>;
     using UT = UpTile<D, CS, CU, TH>;
     using GT = GenTile<D, CS, CU, CO, TH_G>;
-    constexpr int EPB = G::EPB, NF = G::NF, CSTS = G::CSTS, CSTU = G::CSTU;
+    constexpr int EPB = G::EPB, NF = G::NF, SPS = UpTile<D, CS, CU, TH>::SPS, LPS = UpTile<D, CS, CU, TH>::LPS;
     constexpr int RW = TH / 4;                  // rows per wave
     static_assert(TH % 8 == 0 && TH % TH_G == 0, "each wave needs rows of one parity in one half of the tile");
     static_assert(MODE == OutMode::Store || MODE == OutMode::Head, "decoder stages store or end in the head");
@@ -169,15 +172,24 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
         const S* lbase = reinterpret_cast<const S*>(a.low) + (((size_t)n * hl + (y0 >> 1) - 1) * wl + (x0 >> 1) - 1) * CU;
         const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase), lr = buf_rsrc(lbase);
         const int srow = w * CS * (int)sizeof(S), lrow = wl * CU * (int)sizeof(S);
-        auto skip_ld = [&](int r, int k) -> u32x4 { return load_blk<D>(sr, r * srow + k * BB, 0); };
-        auto skip_st = [&](int r, int k, const u32x4& v) {
-            const int c = k / G::BPT_S, cb = k - c * G::BPT_S;
-            *reinterpret_cast<u32x4*>(&skip[((r * 2 + (c & 1)) * UT::SC + (c >> 1)) * CSTS + cb * EPB]) = v;
+        // chunk k = block k / (pixels per row) of pixel k % (pixels per row):
+        // consecutive lanes store one block of consecutive pixels (no bank
+        // conflicts), and a wave's loads still cover whole pixel runs
+        auto skip_ld = [&](int r, int k) -> u32x4 {
+            const int cb = k / 34, c = k - cb * 34;
+            return load_blk<D>(sr, r * srow + (c * G::BPT_S + cb) * BB, 0);
         };
-        auto low_ld = [&](int r, int k) -> u32x4 { return load_blk<D>(lr, r * lrow + k * BB, 0); };
+        auto skip_st = [&](int r, int k, const u32x4& v) {
+            const int cb = k / 34, c = k - cb * 34;
+            *reinterpret_cast<u32x4*>(&skip[cb * SPS + ((r * 2 + (c & 1)) * UT::SC + (c >> 1)) * EPB]) = v;
+        };
+        auto low_ld = [&](int r, int k) -> u32x4 {
+            const int cb = k / UT::LC, c = k - cb * UT::LC;
+            return load_blk<D>(lr, r * lrow + (c * G::BPT_U + cb) * BB, 0);
+        };
         auto low_st = [&](int r, int k, const u32x4& v) {
-            const int c = k / G::BPT_U, cb = k - c * G::BPT_U;
-            *reinterpret_cast<u32x4*>(&lowt[(r * UT::LC + c) * CSTU + cb * EPB]) = v;
+            const int cb = k / UT::LC, c = k - cb * UT::LC;
+            *reinterpret_cast<u32x4*>(&lowt[cb * LPS + (r * UT::LC + c) * EPB]) = v;
         };
         copy_rows2<UT::SR, KS, UT::LR, KL>(skip_ld, skip_st, low_ld, low_st, threadIdx.x);
     }
@@ -215,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
             for (int p = 0; p < 2; ++p) {
                 const int c = p + kx;
                 const u32x4 xb = *reinterpret_cast<const u32x4*>(
-                    &skip[((row * 2 + (c & 1)) * UT::SC + j + (c >> 1)) * CSTS + cb * EPB]);
+                    &skip[cb * SPS + ((row * 2 + (c & 1)) * UT::SC + j + (c >> 1)) * EPB]);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) acc[m][p][f] = mfma_kgroup<D>(wf[f], xb, acc[m][p][f]);
             }
@@ -239,7 +251,7 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
             const int r = RW * half + m + ty;
-            const u32x4 xb = *reinterpret_cast<const u32x4*>(&lowt[(r * UT::LC + j + tx) * CSTU + cb * EPB]);
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&lowt[cb * LPS + (r * UT::LC + j + tx) * EPB]);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 acc[m][0][f] = mfma_kgroup<D>(w0[f], xb, acc[m][0][f]);

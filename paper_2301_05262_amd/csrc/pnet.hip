@@ -52,15 +52,16 @@ template <Dt D, bool IN_F32, int CS, int CU, bool SUM, int C1, int C2, PMode MOD
 __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     using T = typename DT<D>::T;
     using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
-    constexpr int EPB = G::EPB, CST = G::CST, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
+    constexpr int EPB = G::EPB, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
     constexpr int NF2 = (C2 + 15) / 16;
     constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
+    constexpr int PS = plane_stride<D>(NPIX);       // block-major LDS planes
     constexpr int RPW = TH / 4, MF = RPW * 2;
     constexpr bool POOL = MODE == PMode::PoolOnly || MODE == PMode::PoolSkip;
     static_assert(!POOL || RPW == 2, "pooling needs row pairs per wave");
     static_assert(C1 % 16 == 0, "the 1x1 reads whole 16-channel fragments");
 
-    __shared__ __attribute__((aligned(16))) T tile[NPIX * CST];
+    __shared__ __attribute__((aligned(16))) T tile[BPT * PS];
     __shared__ __attribute__((aligned(16))) T lowt[LowTile<D, CU, TH>::SIZE];
 
     const int h = a.h, w = a.w;
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
     const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
 
-    load_halo_tile<D, IN_F32, CS, CU, CST, TH, SUM, S2D>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
+    load_halo_tile<D, IN_F32, CS, CU, EPB, PS, TH, SUM, S2D>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     // the wave index is uniform in the wave: keep it in a scalar register
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -88,11 +89,11 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
         if (b >= NB) b = NB - 1;
         const int tap = b / BPT, cb = b - tap * BPT;
         const int ky = tap / 3, kx = tap - ky * 3;
-        const int base = (ky * WP + kx + px) * CST + cb * EPB;
+        const int base = cb * PS + (ky * WP + kx + px) * EPB;
 #pragma unroll
         for (int m = 0; m < MF; ++m) {
             const int r = wave * RPW + (m >> 1), cf = m & 1;
-            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + (r * WP + cf * 16) * CST]);
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + (r * WP + cf * 16) * EPB]);
 #pragma unroll
             for (int f = 0; f < NF; ++f) acc[m][f] = mfma_kgroup<D>(wf[f], xb, acc[m][f]);
         }
