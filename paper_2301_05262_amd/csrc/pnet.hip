@@ -80,11 +80,19 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     for (int m = 0; m < MF; ++m)
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int q = 0; q < NKG; ++q) {
-        u32x4 wf[NF];
+    // weight fragments are fetched PD k-groups ahead of their MFMAs
+    constexpr int PD = NF <= 2 ? 2 : 1;
+    u32x4 wbuf[PD + 1][NF];
+    auto wload = [&](int q, u32x4 (&dst)[NF]) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) wf[f] = wpk[(f * NKG + q) * 64 + lane];
+        for (int f = 0; f < NF; ++f) dst[f] = wpk[(f * NKG + q) * 64 + lane];
+    };
+#pragma unroll
+    for (int q = 0; q < PD && q < NKG; ++q) wload(q, wbuf[q]);
+#pragma unroll
+    for (int q = 0; q < NKG; ++q) {
+        if (q + PD < NKG) wload(q + PD, wbuf[(q + PD) % (PD + 1)]);
+        const u32x4 (&wf)[NF] = wbuf[q % (PD + 1)];
         int b = 4 * q + g;
         if (b >= NB) b = NB - 1;
         const int tap = b / BPT, cb = b - tap * BPT;
@@ -252,6 +260,141 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     }
 }
 
+// Channel-split form of a wide stored stage (the 5-level network's
+// bottleneck, 3x3 to 256 channels and 1x1 back to 128, at 1/16 of the image
+// size: 64 x 128 pixels at 1024 x 2048).  The row-per-wave kernel above would
+// run there as 64 blocks of one wave per CU.  Here a block is one row of 32
+// pixels and its four waves split the 3x3's output channels: wave w computes
+// fragments [w NF/4, (w+1) NF/4) of the 3x3 for both 16-pixel halves, applies
+// bias and ReLU, and multiplies its channel slice by the matching columns of
+// the 1x1.  The four partial 1x1 sums meet in LDS (the halo tile's memory,
+// reused) and each wave finishes a quarter of the 1x1 outputs, adding the
+// partials in a fixed order: 256 blocks at 64 x 128 pixels.
+template <Dt D, int CS, int C1, int C2>
+__global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
+    using T = typename DT<D>::T;
+    using S = typename ST<D>::S;
+    using G = Geo<D, CS, 0, C1>;
+    constexpr int TH = 1, MF = 2;
+    constexpr int EPB = G::EPB, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
+    constexpr int NFW = NF / 4, NF2 = C2 / 16, N2W = NF2 / 4;
+    static_assert(NF % 4 == 0 && C2 % 64 == 0, "four waves split whole fragments");
+    constexpr int WP = kTW + 2, NPIX = (TH + 2) * WP;
+    constexpr int PS = plane_stride<D>(NPIX);
+    constexpr int TILE_BYTES = BPT * PS * (int)sizeof(T);
+    constexpr int RED_BYTES = 4 * MF * NF2 * 64 * 16;
+    constexpr int SMEM = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+    __shared__ __attribute__((aligned(16))) T lowt[1];
+    T* tile = reinterpret_cast<T*>(smem);
+
+    const int h = a.h, w = a.w;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
+    load_halo_tile<D, false, CS, 0, EPB, PS, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int px = lane & 15, g = lane >> 4;
+    const u32x4* wpk = reinterpret_cast<const u32x4*>(a.wpk);
+    f32x4 acc[MF][NFW];
+#pragma unroll
+    for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f = 0; f < NFW; ++f) acc[m][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // one block per CU leaves no other wave to cover the weight loads: fetch
+    // the fragments PD k-groups ahead of their MFMAs
+    constexpr int PD = 4;
+    u32x4 wbuf[PD + 1][NFW];
+    auto wload = [&](int q, u32x4 (&dst)[NFW]) {
+#pragma unroll
+        for (int f = 0; f < NFW; ++f) dst[f] = wpk[((wave * NFW + f) * NKG + q) * 64 + lane];
+    };
+#pragma unroll
+    for (int q = 0; q < PD && q < NKG; ++q) wload(q, wbuf[q]);
+#pragma unroll
+    for (int q = 0; q < NKG; ++q) {
+        if (q + PD < NKG) wload(q + PD, wbuf[(q + PD) % (PD + 1)]);
+        const u32x4 (&wf)[NFW] = wbuf[q % (PD + 1)];
+        int b = 4 * q + g;
+        if (b >= NB) b = NB - 1;
+        const int tap = b / BPT, cb = b - tap * BPT;
+        const int ky = tap / 3, kx = tap - ky * 3;
+        const int base = cb * PS + (ky * WP + kx + px) * EPB;
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + m * 16 * EPB]);
+#pragma unroll
+            for (int f = 0; f < NFW; ++f) acc[m][f] = mfma_kgroup<D>(wf[f], xb, acc[m][f]);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NFW; ++f) {
+        float bb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bb[e] = a.b1[(wave * NFW + f) * 16 + 4 * g + e];
+#pragma unroll
+        for (int m = 0; m < MF; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[m][f][e] = fmaxf(acc[m][f][e] + bb[e], 0.0f);
+    }
+    // partial 1x1 over this wave's channel slice
+    f32x4 acc2[MF][NF2];
+#pragma unroll
+    for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f2 = 0; f2 < NF2; ++f2) acc2[m][f2] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int f2 = 0; f2 < NF2; ++f2) {
+#pragma unroll
+        for (int f = 0; f < NFW; ++f) {
+            const int fg = wave * NFW + f;
+            if constexpr (D == Dt::F32) {
+                const f32x4 w4 = reinterpret_cast<const f32x4*>(a.w1pk)[(f2 * NF + fg) * 64 + lane];
+#pragma unroll
+                for (int m = 0; m < MF; ++m)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc2[m][f2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[e], acc[m][f][e], acc2[m][f2], 0, 0, 0);
+            } else {
+                const uint2 w4 = reinterpret_cast<const uint2*>(a.w1pk)[(f2 * NF + fg) * 64 + lane];
+#pragma unroll
+                for (int m = 0; m < MF; ++m) acc2[m][f2] = mfma_1x1<D>(w4, acc[m][f], acc2[m][f2]);
+            }
+        }
+    }
+    // the four partials meet in LDS; wave w finishes fragments [w N2W, (w+1) N2W)
+    __syncthreads();                           // every wave is done reading the tile
+    f32x4* red = reinterpret_cast<f32x4*>(smem);
+#pragma unroll
+    for (int m = 0; m < MF; ++m)
+#pragma unroll
+        for (int f2 = 0; f2 < NF2; ++f2) red[((wave * MF + m) * NF2 + f2) * 64 + lane] = acc2[m][f2];
+    __syncthreads();
+    S* out = reinterpret_cast<S*>(a.out);
+#pragma unroll
+    for (int k = 0; k < N2W; ++k) {
+        const int f2 = wave * N2W + k, co = f2 * 16 + 4 * g;
+        float bb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bb[e] = a.b2[co + e];
+#pragma unroll
+        for (int m = 0; m < MF; ++m) {
+            f32x4 v = red[((0 * MF + m) * NF2 + f2) * 64 + lane];
+#pragma unroll
+            for (int wv = 1; wv < 4; ++wv) v += red[((wv * MF + m) * NF2 + f2) * 64 + lane];
+            const int x = x0 + m * 16 + px;
+            if (y0 < h && x < w) {
+                float v4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v4[e] = fmaxf(v[e] + bb[e], 0.0f);
+                const size_t p = ((size_t)n * h + y0) * w + x;
+                store4<S, C2>(out + p * C2 + co, co, v4);
+            }
+        }
+    }
+}
+
 // Depth-to-space head of the space-to-depth form (Sec. 3.5).  One thread per
 // low-resolution pixel (i, j) writes the 2x2 block (2i + dy, 2j + dx):
 // logit = bilinear x2 of channel 0 (the taps of the decoder's upsampling:
@@ -339,15 +482,29 @@ template <Dt D> constexpr const char* pdt_suffix() {
 
 template <Dt D>
 hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* found) {
+    // the 256-channel bottleneck runs in the channel-split form (same packed weights)
+    if (st.cs == 128 && st.cu == 0 && !st.sum && st.c1 == 256 && st.c2 == 128 && st.mode == PMode::Store &&
+        !st.in_f32 && !st.s2d) {
+        *found = true;
+        dim3 grid((a.w + kTW - 1) / kTW, a.h, a.n);
+        TraceScope ts("pconv 128+0->256->128 Store split", pdt_suffix<D>(), s);
+        k_pconv_cs<D, 128, 256, 128><<<grid, kThreads, 0, s>>>(a);
+        return hipGetLastError();
+    }
 #define NSM_PCASE(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_)                               \
     if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)) {                                \
         *found = true;                                                                            \
-        dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH_ - 1) / TH_, a.n);                             \
-        TraceScope ts(S2D_ ? "pconv s2d " #CS_ "->" #C1_ "->" #C2_ " " #MODE_                     \
-                           : "pconv " #CS_ "+" #CU_ "->" #C1_ "->" #C2_ " " #MODE_,               \
-                      pdt_suffix<D>(), s);                                                        \
-        k_pconv<D, F32_, CS_, CU_, SUM_, C1_, C2_, PMode::MODE_, TH_, S2D_><<<grid, kThreads, 0, s>>>(a); \
-        return hipGetLastError();                                                                 \
+        if constexpr (C1_ >= 256) {     /* 256-wide stages run in the channel-split form */       \
+            return hipErrorInvalidValue;                                                          \
+        } else {                                                                                  \
+            dim3 grid((a.w + kTW - 1) / kTW, (a.h + TH_ - 1) / TH_, a.n);                         \
+            TraceScope ts(S2D_ ? "pconv s2d " #CS_ "->" #C1_ "->" #C2_ " " #MODE_                 \
+                               : "pconv " #CS_ "+" #CU_ "->" #C1_ "->" #C2_ " " #MODE_,           \
+                          pdt_suffix<D>(), s);                                                    \
+            k_pconv<D, F32_, CS_, CU_, SUM_, C1_, C2_, PMode::MODE_, TH_, S2D_>                   \
+                <<<grid, kThreads, 0, s>>>(a);                                                    \
+            return hipGetLastError();                                                             \
+        }                                                                                         \
     }
     NSM_PSTAGES(NSM_PCASE)
 #undef NSM_PCASE
