@@ -11,13 +11,17 @@ namespace {
 using namespace ck;
 // ---------------------------------------------------------------- dispatch
 // Supported stages: (cs, cu, co, mode, float32 input, tile rows) per dtype.
+// For decoder stages the tile rows are those of the general kernel's border
+// tiles; 4 rows keep the 16+32 stage's border tile below its phase tile in
+// LDS, so that four blocks fit per CU (the 32+64 stage's border tile, at
+// the minimum of 4 rows, still sets its LDS size).
 #define NSM_STAGES(X)                           \
     X(6, 0, 16, Pool, true, 8)                  \
     X(8, 0, 16, Pool, true, 8)                  \
     X(16, 0, 32, Pool, false, 8)                \
     X(32, 0, 64, Store, false, 8)               \
     X(32, 64, 32, Store, false, 4)              \
-    X(16, 32, 16, Head, false, 8)               \
+    X(16, 32, 16, Head, false, 4)               \
     X(6, 0, 8, Pool, true, 8)                   \
     X(8, 0, 16, Store, false, 8)                \
     X(8, 16, 8, Head, false, 8)
