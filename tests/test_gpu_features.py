@@ -2,8 +2,9 @@
 
 Shadow map depth bits, camera key buffer, every float32 feature channel and
 the depth-test mask must equal the oracle's bit for bit, on the tiny scenes,
-the 1080p scene with a 2048^2 map, a soft-shadow frame, a ragged screen and
-an empty scene; repeated calls must be identical.
+the 1080p scene with a 2048^2 map, a soft-shadow frame, a ragged screen, an
+empty scene and the largest targets the ABI accepts; repeated calls must be
+identical.
 """
 import numpy as np
 import pytest
@@ -91,3 +92,22 @@ def test_empty_scene():
     _compare(got, ref, "empty")
     assert (got["gbuf"] == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
     assert (got["feat"] == 0).all()
+
+
+def test_maximum_target_sizes():
+    """The largest targets the ABI accepts, 16384 texels a side: a 16384^2
+    shadow map (snapped coordinates reach ~2^22 in 24.8 fixed point, the
+    largest edge-function terms of the exactness argument) and a screen
+    16384 pixels wide, of ragged height (the largest row offsets of the
+    64-bit key buffer); a narrow vertical field of view keeps the scene
+    across the whole width."""
+    sc = S.make_scene("tiny", 0)
+    fr = S.make_frame(sc, 16384, 1003, 16384, light_pos=(0.3, 3.0, -0.2), eye=(3.0, 1.5, 0.5),
+                      target=(0.0, -0.9, 0.0), vfov_deg=8.0)
+    ref = oracle.build_features(sc, fr)
+    got = _to_np(_builder(sc)(fr))
+    covered = int((ref["sm"] != 0x7F800000).sum())
+    seen = int((ref["gbuf"] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+    print(f"[max] shadow-map texels covered {covered}, camera pixels with a receiver {seen}", flush=True)
+    assert covered > 10_000_000 and seen > 1_000_000
+    _compare(got, ref, "max")

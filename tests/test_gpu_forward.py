@@ -4,7 +4,8 @@ FP32: max |gpu - oracle| <= 1e-5 * max |oracle| on logits and on visibility
 (norm-wise, per tensor).  BF16 / FP16 (precision form): max |vis - vis_fp64|
 <= 2e-2 over all pixels, reported beside the storage-rounding emulation.
 Shapes cover several tiles with ragged tails, batches, the tiny 64x64 U2
-workload, the 1080p U3 workload bench.py times, and the soft 8-channel net.
+workload, the 1080p U3 workload bench.py times, the soft 8-channel net, and
+the widest and tallest screens the ABI accepts (16384 pixels).
 """
 import numpy as np
 import pytest
@@ -55,6 +56,24 @@ def test_fp32_random_features(desc, shape):
     ref = onet.forward(desc.c_in, desc.widths, flat, feat, keep=False)
     vis, lg = _run(_net(desc, "f32", flat), feat)
     _check_fp32(vis, lg, ref, f"{desc.widths}/{shape}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("h,w", [(20, 16384), (16384, 20)])
+def test_maximum_screen_extent(h, w, dtype):
+    """16384 pixels along one side (the ABI maximum) at a ragged other side:
+    the largest row strides and tile counts of every stage (the other side, 20,
+    is not a multiple of the 8-row or 32-pixel tiles)."""
+    flat = S.he_weights(S.U3, 13, bias_scale=0.1)
+    feat = _rand_feat(1, h, w, S.U3.c_in, 14)
+    ref = onet.forward(S.U3.c_in, S.U3.widths, flat, feat, keep=False)
+    vis, lg = _run(_net(S.U3, dtype, flat), feat)
+    if dtype == "f32":
+        _check_fp32(vis, lg, ref, f"{h}x{w}")
+    else:
+        err = np.abs(vis - ref["vis"]).max()
+        print(f"[{h}x{w}/{dtype}] max |vis - vis_fp64| {err:.3e}", flush=True)
+        assert err <= LOWP_ABS
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
