@@ -718,11 +718,19 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
                 const int yp = (y0 >> 1) + wave * (RPW / 2) + pr, xp = ((x0 + cf * 16 + px) >> 1);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
+                    // 2x2 max of ReLU outputs: non-negative and never NaN, so
+                    // their float order is the order of their bit patterns as
+                    // signed integers (a -0 sorts below +0 and pools to the
+                    // same value); integer max needs no NaN canonicalisation,
+                    // and the neighbouring column is lane ^ 1 (a DPP quad
+                    // permute instead of an LDS shuffle)
                     float mx[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const float v = fmaxf(acc[4 * pr + cf][f][e], acc[4 * pr + 2 + cf][f][e]);
-                        mx[e] = fmaxf(v, __shfl_xor(v, 1));
+                        const int v = max(__float_as_int(acc[4 * pr + cf][f][e]),
+                                          __float_as_int(acc[4 * pr + 2 + cf][f][e]));
+                        const int o = __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+                        mx[e] = __int_as_float(max(v, o));
                     }
                     const int co = f * 16 + 4 * g;
                     if ((px & 1) == 0 && yp < hp && xp < wp && co < CO) {
