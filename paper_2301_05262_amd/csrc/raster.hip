@@ -29,7 +29,9 @@ namespace {
 constexpr uint32_t kEmptyDepth = 0x7F800000u;
 constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr int kScanThreads = 1024;
+constexpr int kSetupThreads = 64;     // one wave per setup block: more waves in flight per CU
 constexpr int kGroup = 32;            // virtual triangles per group of the item -> triangle search
+static_assert(kSetupThreads % kGroup == 0, "a search group must lie inside one setup block");
 constexpr int kRasterBlocks = 2048;   // 8192 waves: 32 per CU on 256 CUs, one resident round
 constexpr int kStep = 2;              // tile items evaluated together in the walk
 
@@ -100,22 +102,24 @@ __device__ __forceinline__ int tri_setup_one(const float* __restrict__ tris, int
     const float fw = (float)w, fh = (float)h;
     int64_t X[3], Y[3];
     float Z[3];
+    // the three vertices are transformed without early exits so that their
+    // independent divisions overlap; a dropped triangle's values are unused
     bool drop = false;
+#pragma unroll
     for (int v = 0; v < 3; ++v) {
         float c[4];
         to_clip(M, T[3 * v], T[3 * v + 1], T[3 * v + 2], c);
-        if (!(c[3] > 1e-6f)) { drop = true; break; }
-        float nx = c[0] / c[3];
-        float ny = c[1] / c[3];
-        float nz = c[2] / c[3];
+        const bool front = c[3] > 1e-6f;
+        const float w = front ? c[3] : 1.0f;
+        float nx = c[0] / w;
+        float ny = c[1] / w;
+        float nz = c[2] / w;
         float sx = (nx * 0.5f + 0.5f) * fw;
         float sy = (ny * 0.5f + 0.5f) * fh;
-        if (!(sx >= -8.0f * fw && sx <= 9.0f * fw && sy >= -8.0f * fh && sy <= 9.0f * fh)) {
-            drop = true;
-            break;
-        }
-        X[v] = (int64_t)rintf(sx * 256.0f);
-        Y[v] = (int64_t)rintf(sy * 256.0f);
+        const bool inside = sx >= -8.0f * fw && sx <= 9.0f * fw && sy >= -8.0f * fh && sy <= 9.0f * fh;
+        drop = drop || !front || !inside;
+        X[v] = inside ? (int64_t)rintf(sx * 256.0f) : 0;
+        Y[v] = inside ? (int64_t)rintf(sy * 256.0f) : 0;
         Z[v] = nz;
     }
     int count = 0;
@@ -176,28 +180,23 @@ __device__ __forceinline__ int tri_setup_one(const float* __restrict__ tris, int
     return count;
 }
 
-// Block-local exclusive scan of one int per thread (256 threads); returns the
-// thread's offset and writes the block total to *total (all threads call it).
-__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
-    __shared__ int wsum[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Exclusive scan of one int per lane of a one-wave block; returns the lane's
+// offset and writes the wave total to *total (all lanes call it).
+__device__ __forceinline__ int wave_exclusive_scan(int v, int* total) {
+    const int lane = threadIdx.x & 63;
     int incl = v;
     for (int d = 1; d < 64; d <<= 1) {
         const int u = __shfl_up(incl, d);
         if (lane >= d) incl += u;
     }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int off = 0;
-    for (int k = 0; k < wave; ++k) off += wsum[k];
-    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    return off + incl - v;
+    *total = __shfl(incl, 63);
+    return incl - v;
 }
 
 // Blocks [0, nblk) set up one virtual triangle per thread (v = pass * n_tris
 // + t) and scan their tile counts; the remaining blocks clear the targets.
 // The raster kernel that follows on the stream sees both finished.
-__global__ void __launch_bounds__(256) k_tri_setup(const float* __restrict__ tris, int n_tris,
+__global__ void __launch_bounds__(kSetupThreads) k_tri_setup(const float* __restrict__ tris, int n_tris,
                                                    RasterPasses P, TriSetup* __restrict__ setup,
                                                    TriCoef* __restrict__ coef,
                                                    int* __restrict__ local_off, int* __restrict__ block_sum,
@@ -216,7 +215,7 @@ __global__ void __launch_bounds__(256) k_tri_setup(const float* __restrict__ tri
                               coef + pass * n_tris);
     }
     int total;
-    const int off = block_exclusive_scan(count, &total);
+    const int off = wave_exclusive_scan(count, &total);
     if (v < P.npass * n_tris) local_off[v] = off;
     if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
 }
@@ -256,7 +255,7 @@ __global__ void __launch_bounds__(kScanThreads) k_block_scan(const int* __restri
     const int ngroups = (nv + kGroup - 1) / kGroup;
     for (int g = tid; g <= ngroups; g += kScanThreads) {
         const int t = g * kGroup;
-        gbase[g] = (t < nv) ? base[t >> 8] + local_off[t] : carry;
+        gbase[g] = (t < nv) ? base[t / kSetupThreads] + local_off[t] : carry;
     }
 }
 
@@ -625,7 +624,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 size_t raster_workspace_bytes(int n_tris) {
-    const size_t nv = 2 * (size_t)n_tris, nblk = (nv + 255) / 256, ng = (nv + kGroup - 1) / kGroup;
+    const size_t nv = 2 * (size_t)n_tris, nblk = (nv + kSetupThreads - 1) / kSetupThreads,
+                 ng = (nv + kGroup - 1) / kGroup;
     return align256(nv * sizeof(TriSetup)) + align256(nv * sizeof(TriCoef)) + align256(nv * 4) +
            align256(nblk * 4) + align256((nblk + 1) * 8) + align256((ng + 1) * 8);
 }
@@ -642,7 +642,7 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
         most = max(most, f[k].bytes);
     }
     const int nv = P.npass * n_tris;
-    const int nblk = (nv + 255) / 256;
+    const int nblk = (nv + kSetupThreads - 1) / kSetupThreads;
     char* wsb = reinterpret_cast<char*>(ws);
     TriSetup* setup = reinterpret_cast<TriSetup*>(wsb);
     wsb += align256((size_t)nv * sizeof(TriSetup));
@@ -657,8 +657,8 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     long long* gbase = reinterpret_cast<long long*>(wsb);
     {
         TraceScope ts("setup+clear", sfx, s);
-        const int fill_blocks = (int)min((size_t)1024, (most / 16 + 255) / 256 + 1);
-        k_tri_setup<<<nblk + fill_blocks, 256, 0, s>>>(tris, n_tris, P, setup, coef, local_off, block_sum, nblk,
+        const int fill_blocks = (int)min((size_t)4096, (most / 16 + kSetupThreads - 1) / kSetupThreads + 1);
+        k_tri_setup<<<nblk + fill_blocks, kSetupThreads, 0, s>>>(tris, n_tris, P, setup, coef, local_off, block_sum, nblk,
                                                        f[0], f[1]);
     }
     if (n_tris == 0) return hipGetLastError();
