@@ -346,8 +346,9 @@ def paper_net_section(S, torch, seed, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path has no multi-GPU "
-              "mode in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no "
+              "multi-GPU mode; frames are independent, so a caller shards them over one process "
+              "per GPU", file=sys.stderr)
         sys.exit(2)
     import torch
 

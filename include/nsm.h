@@ -48,7 +48,7 @@ typedef enum {
     NSM_OK = 0,
     NSM_E_INVALID_ARG = 1,  /* null pointer, negative size, bad enum value      */
     NSM_E_SHAPE = 2,        /* H or W not divisible by 2^(levels-1), size limits */
-    NSM_E_UNSUPPORTED = 3,  /* network or dtype this build has no kernels for    */
+    NSM_E_UNSUPPORTED = 3,  /* network or dtype the library has no kernels for   */
     NSM_E_WORKSPACE = 4,    /* workspace missing or smaller than required        */
     NSM_E_NO_WEIGHTS = 5,   /* nsm_set_weights has not been called               */
     NSM_E_DEVICE = 6,       /* no HIP device, or a HIP runtime call failed       */
