@@ -31,7 +31,7 @@ struct TraceScope {
 struct alignas(16) TriSetup {
     int32_t x[3], y[3];   // 24.8 fixed-point screen coordinates, CCW order
     float z[3];           // ndc depth per vertex
-    int32_t tx0, ty0;     // first 8x8 tile of the texel bounding box
+    int32_t tx0, ty0;     // first raster tile of the texel bounding box
     int32_t ntx;          // tiles per bounding-box row (count = ntx * nty)
     int64_t area;         // doubled signed area (> 0 after reordering)
     int32_t pad;
