@@ -200,36 +200,46 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int j = lane & 15, g = lane >> 4;
     const int py = wave & 1, half = wave >> 1;
-    f32x4 acc[RW][2][NF];
+    // Stored stages with an even number of 16-channel fragments split the
+    // output channels, not the rows, between the two waves of a row parity:
+    // each wave streams half of the weights from L2 (the weight fragments,
+    // not the MFMAs, fill the vector memory pipe) and reads twice the
+    // activation fragments from LDS, which has the bandwidth to spare.
+    constexpr bool SPLIT = MODE == OutMode::Store && NF % 2 == 0;
+    constexpr int MR = SPLIT ? 2 * RW : RW;         // rows of parity py per wave
+    constexpr int NFW = SPLIT ? NF / 2 : NF;        // 16-channel fragments per wave
+    const int f0 = SPLIT ? half * NFW : 0;          // the wave's first fragment
+    const int rb = SPLIT ? 0 : RW * half;           // the wave's first row of parity py
+    f32x4 acc[MR][2][NFW];
 #pragma unroll
-    for (int m = 0; m < RW; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int f = 0; f < NF; ++f) acc[m][p][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int f = 0; f < NFW; ++f) acc[m][p][f] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // skip channels: ordinary 3x3 taps over the full-resolution tile
     const __amdgpu_buffer_rsrc_t wr = buf_rsrc(wup);
     const int wl16 = lane * 16;
 #pragma unroll
     for (int q = 0; q < G::NKG_S; ++q) {
-        u32x4 wf[NF];
+        u32x4 wf[NFW];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) wf[f] = buf_load16(wr, wl16, (f * G::NKG_S + q) * 1024);
+        for (int f = 0; f < NFW; ++f) wf[f] = buf_load16(wr, wl16, ((f0 + f) * G::NKG_S + q) * 1024);
         int b = 4 * q + g;
         if (b >= G::NB_S) b = G::NB_S - 1;     // padding k: weights are zero there
         const int tap = b / G::BPT_S, cb = b - tap * G::BPT_S;
         const int ky = tap / 3, kx = tap - ky * 3;
 #pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            const int row = py + 2 * (RW * half + m) + ky;
+        for (int m = 0; m < MR; ++m) {
+            const int row = py + 2 * (rb + m) + ky;
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
                 const int c = p + kx;
                 const u32x4 xb = *reinterpret_cast<const u32x4*>(
                     &skip[cb * SPS + ((row * 2 + (c & 1)) * UT::SC + j + (c >> 1)) * EPB]);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) acc[m][p][f] = mfma_kgroup<D>(wf[f], xb, acc[m][p][f]);
+                for (int f = 0; f < NFW; ++f) acc[m][p][f] = mfma_kgroup<D>(wf[f], xb, acc[m][p][f]);
             }
         }
     }
@@ -238,22 +248,22 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     const int wph = WLO + py * 2 * NF * G::NKG_U * 1024;        // this wave's row phase
 #pragma unroll
     for (int q = 0; q < G::NKG_U; ++q) {
-        u32x4 w0[NF], w1[NF];
+        u32x4 w0[NFW], w1[NFW];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            w0[f] = buf_load16(wr, wl16, wph + (f * G::NKG_U + q) * 1024);
-            w1[f] = buf_load16(wr, wl16, wph + ((NF + f) * G::NKG_U + q) * 1024);
+        for (int f = 0; f < NFW; ++f) {
+            w0[f] = buf_load16(wr, wl16, wph + ((f0 + f) * G::NKG_U + q) * 1024);
+            w1[f] = buf_load16(wr, wl16, wph + ((NF + f0 + f) * G::NKG_U + q) * 1024);
         }
         int b = 4 * q + g;
         if (b >= G::NB_U) b = G::NB_U - 1;
         const int t = b / G::BPT_U, cb = b - t * G::BPT_U;
         const int ty = t / 3, tx = t - ty * 3;
 #pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            const int r = RW * half + m + ty;
+        for (int m = 0; m < MR; ++m) {
+            const int r = rb + m + ty;
             const u32x4 xb = *reinterpret_cast<const u32x4*>(&lowt[cb * LPS + (r * UT::LC + j + tx) * EPB]);
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
+            for (int f = 0; f < NFW; ++f) {
                 acc[m][0][f] = mfma_kgroup<D>(w0[f], xb, acc[m][0][f]);
                 acc[m][1][f] = mfma_kgroup<D>(w1[f], xb, acc[m][1][f]);
             }
@@ -261,20 +271,20 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     }
 
     // ---------------- epilogue: bias + ReLU, then store or the 1x1 head
-    float bias[NF][4];
+    float bias[NFW][4];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NFW; ++f)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int co = f * 16 + 4 * g + e;
+            const int co = (f0 + f) * 16 + 4 * g + e;
             bias[f][e] = (co < CO) ? a.bias[co] : 0.0f;
         }
 #pragma unroll
-    for (int m = 0; m < RW; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
+            for (int f = 0; f < NFW; ++f)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[m][p][f][e] = fmaxf(acc[m][p][f][e] + bias[f][e], 0.0f);
 
@@ -341,15 +351,15 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
         constexpr int SZ = (int)sizeof(S);
         const __amdgpu_buffer_rsrc_t orc =
             buf_rsrc(reinterpret_cast<S*>(a.out) + (((size_t)n * h + y0) * w + x0) * CO);
-        const int voff = (((py + 2 * RW * half) * w + 2 * j) * CO + 4 * g) * SZ;
+        const int voff = (((py + 2 * rb) * w + 2 * j) * CO + 4 * g) * SZ;
         const int rstep = 2 * w * CO * SZ;
 #pragma unroll
-        for (int m = 0; m < RW; ++m)
+        for (int m = 0; m < MR; ++m)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int f = 0; f < NF; ++f)
-                    buf_store4<S>(orc, voff, m * rstep + (p * CO + f * 16) * SZ, acc[m][p][f]);
+                for (int f = 0; f < NFW; ++f)
+                    buf_store4<S>(orc, voff, m * rstep + (p * CO + (f0 + f) * 16) * SZ, acc[m][p][f]);
     }
 }
 
