@@ -37,7 +37,9 @@ constexpr int kTileW = 16, kTileH = 4;
 static_assert(kTileW * kTileH == 64, "one texel per lane of a wave");
 constexpr int kGroup = 32;            // virtual triangles per group of the item -> triangle search
 static_assert(kSetupThreads % kGroup == 0, "a search group must lie inside one setup block");
-constexpr int kRasterBlocks = 2048;   // 8192 waves: 32 per CU on 256 CUs, one resident round
+// 8192 waves; registers and LDS leave 6 resident per SIMD (6144 on 256 CUs),
+// enough for the ~5300 chunks of a 1080p frame in one round
+constexpr int kRasterBlocks = 2048;
 constexpr int kStep = 2;              // tile items evaluated together in the walk
 
 __device__ __forceinline__ void to_clip(const Mat4& M, float x, float y, float z, float c[4]) {
