@@ -270,12 +270,17 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
 // the 1x1.  The four partial 1x1 sums meet in LDS (the halo tile's memory,
 // reused) and each wave finishes a quarter of the 1x1 outputs, adding the
 // partials in a fixed order: 256 blocks at 64 x 128 pixels.
-template <Dt D, int CS, int C1, int C2>
+//
+// Decoder stages with a summed skip (input = skip + bilinear x2 of the
+// low-resolution tensor) use the same split with two-row tiles (CU > 0,
+// SUM): the low-resolution rows of a one-row tile would not cover its halo.
+template <Dt D, int CS, int CU, bool SUM, int C1, int C2, int TH>
 __global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
     using T = typename DT<D>::T;
     using S = typename ST<D>::S;
-    using G = Geo<D, CS, 0, C1>;
-    constexpr int TH = 1, MF = 2;
+    using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
+    static_assert(CU == 0 || (SUM && CU == CS && TH % 2 == 0), "summed decoder stages use even tile rows");
+    constexpr int MF = 2 * TH;
     constexpr int EPB = G::EPB, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
     constexpr int NFW = NF / 4, NF2 = C2 / 16, N2W = NF2 / 4;
     static_assert(NF % 4 == 0 && C2 % 64 == 0, "four waves split whole fragments");
@@ -285,14 +290,14 @@ __global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
     constexpr int RED_BYTES = 4 * MF * NF2 * 64 * 16;
     constexpr int SMEM = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
-    __shared__ __attribute__((aligned(16))) T lowt[1];
+    __shared__ __attribute__((aligned(16))) T lowt[LowTile<D, CU, TH>::SIZE];
     T* tile = reinterpret_cast<T*>(smem);
 
     const int h = a.h, w = a.w;
     const int gx = gridDim.x, gy = gridDim.y;
     const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
     const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
-    load_halo_tile<D, false, CS, 0, EPB, PS, TH>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
+    load_halo_tile<D, false, CS, CU, EPB, PS, TH, SUM>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int px = lane & 15, g = lane >> 4;
@@ -323,7 +328,8 @@ __global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
         const int base = cb * PS + (ky * WP + kx + px) * EPB;
 #pragma unroll
         for (int m = 0; m < MF; ++m) {
-            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + m * 16 * EPB]);
+            // fragment m: row m / 2 of the tile, 16-pixel half m % 2
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&tile[base + ((m >> 1) * WP + (m & 1) * 16) * EPB]);
 #pragma unroll
             for (int f = 0; f < NFW; ++f) acc[m][f] = mfma_kgroup<D>(wf[f], xb, acc[m][f]);
         }
@@ -383,12 +389,12 @@ __global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
             f32x4 v = red[((0 * MF + m) * NF2 + f2) * 64 + lane];
 #pragma unroll
             for (int wv = 1; wv < 4; ++wv) v += red[((wv * MF + m) * NF2 + f2) * 64 + lane];
-            const int x = x0 + m * 16 + px;
-            if (y0 < h && x < w) {
+            const int y = y0 + (m >> 1), x = x0 + (m & 1) * 16 + px;
+            if (y < h && x < w) {
                 float v4[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v4[e] = fmaxf(v[e] + bb[e], 0.0f);
-                const size_t p = ((size_t)n * h + y0) * w + x;
+                const size_t p = ((size_t)n * h + y) * w + x;
                 store4<S, C2>(out + p * C2 + co, co, v4);
             }
         }
@@ -488,7 +494,18 @@ hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* fo
         *found = true;
         dim3 grid((a.w + kTW - 1) / kTW, a.h, a.n);
         TraceScope ts("pconv 128+0->256->128 Store split", pdt_suffix<D>(), s);
-        k_pconv_cs<D, 128, 256, 128><<<grid, kThreads, 0, s>>>(a);
+        k_pconv_cs<D, 128, 0, false, 256, 128, 1><<<grid, kThreads, 0, s>>>(a);
+        return hipGetLastError();
+    }
+    // so does the level-3 decoder (128 + up 128 summed -> 128 -> 64), two rows per
+    // block, in the 16-bit forms (in float32 its tile allows one block per CU,
+    // and the row-tile kernel measured faster)
+    if (D != Dt::F32 && st.cs == 128 && st.cu == 128 && st.sum && st.c1 == 128 && st.c2 == 64 &&
+        st.mode == PMode::Store && !st.in_f32 && !st.s2d) {
+        *found = true;
+        dim3 grid((a.w + kTW - 1) / kTW, (a.h + 1) / 2, a.n);
+        TraceScope ts("pconv 128+128->128->64 Store split", pdt_suffix<D>(), s);
+        k_pconv_cs<D, 128, 128, true, 128, 64, 2><<<grid, kThreads, 0, s>>>(a);
         return hipGetLastError();
     }
 #define NSM_PCASE(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_)                               \
