@@ -387,9 +387,10 @@ __device__ __forceinline__ void raster_store(const Frag& f, bool k0, bool k1, vo
 // fire-and-forget integer atomicMin.
 //
 // All coverage arithmetic is float64 on exact integers: snapped coordinates
-// lie in the guard band, below 2^26 in magnitude for targets up to 16384
-// texels, so every product and partial sum of E_k is an integer under 2^53
-// and each E_k is exact (what 64-bit integer arithmetic gives).  The depth
+// lie in the guard band [-8 S, 9 S] (S <= 16384 texels, 8 subpixel bits), so
+// |X| < 2^25.2, edge deltas are below 2^26.1, |c_k| < 2^52.3 and, with texel
+// centres below 2^22, every product and partial sum of E_k is an integer
+// under 2^53: each E_k is exact (what 64-bit integer arithmetic gives).  The depth
 // quotient num / area is rounded correctly with one fused correction of
 // num * (1 / area) (Markstein's theorem: the reciprocal is rounded to nearest
 // and the first quotient is within one ulp), so it equals the IEEE division.
