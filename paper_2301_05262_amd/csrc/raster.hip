@@ -309,8 +309,8 @@ __device__ __forceinline__ int bcast(int v, int lane) { return __builtin_amdgcn_
 // test: E_k is largest at one corner of the tile's texel-centre box (the
 // corner chosen by the signs of dx_k and -dy_k), and E_k <= t_k there means
 // E_k > t_k holds on none of the 64 texels, so the item covers nothing.  The
-// corner is a texel centre within 15 texels of the target, so E_k is exact
-// there as in the walk (an integer below 2^53).
+// corner is a texel centre within 15 texels of the target (below 2^23 in
+// 24.8 fixed point), so E_k is exact there as in the walk.
 __device__ __forceinline__ bool tile_live(const TriCoef& c, int tx, int ty) {
     const double xa = (double)(256 * (kTileW * tx) + 128), xb = xa + (double)(256 * (kTileW - 1));
     const double ya = (double)(256 * (kTileH * ty) + 128), yb = ya + (double)(256 * (kTileH - 1));
@@ -389,8 +389,9 @@ __device__ __forceinline__ void raster_store(const Frag& f, bool k0, bool k1, vo
 // All coverage arithmetic is float64 on exact integers: snapped coordinates
 // lie in the guard band [-8 S, 9 S] (S <= 16384 texels, 8 subpixel bits), so
 // |X| < 2^25.2, edge deltas are below 2^26.1, |c_k| < 2^52.3 and, with texel
-// centres below 2^22, every product and partial sum of E_k is an integer
-// under 2^53: each E_k is exact (what 64-bit integer arithmetic gives).  The depth
+// centres (and the culling test's tile corners) below 2^23, every product and
+// partial sum of E_k is an integer under 2^53: each E_k is exact (what 64-bit
+// integer arithmetic gives).  The depth
 // quotient num / area is rounded correctly with one fused correction of
 // num * (1 / area) (Markstein's theorem: the reciprocal is rounded to nearest
 // and the first quotient is within one ulp), so it equals the IEEE division.
