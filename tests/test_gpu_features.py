@@ -111,3 +111,50 @@ def test_maximum_target_sizes():
     print(f"[max] shadow-map texels covered {covered}, camera pixels with a receiver {seen}", flush=True)
     assert covered > 10_000_000 and seen > 1_000_000
     _compare(got, ref, "max")
+
+
+def _ortho(width, height):
+    """World (x, y, z) -> clip with w = 1, screen position (x, y) in texels and
+    ndc depth z: every step is exact for the dyadic coordinates used below."""
+    m = np.zeros((4, 4), np.float32)
+    m[0, 0], m[0, 3] = 2.0 / width, -1.0
+    m[1, 1], m[1, 3] = 2.0 / height, -1.0
+    m[2, 2] = m[3, 3] = 1.0
+    return m
+
+
+def test_tile_boundaries_and_ties():
+    """Hand-placed triangles under an orthographic matrix, so that vertices sit
+    exactly on texel centres: edges through texel centres (the tie rule), a
+    shared diagonal edge (each texel on it owned by one triangle), edges along
+    the rows and columns where raster tiles meet, slivers whose bounding-box
+    tiles are mostly empty (the tile culling test) and a triangle whose only
+    candidate texel is a tile's corner.  Shadow map and key buffer bit-exact."""
+    import dataclasses
+    T = [
+        [(0.5, 0.5, 0.25), (32.5, 0.5, 0.5), (0.5, 16.5, 0.75)],        # hypotenuse through texel centres
+        [(32.5, 0.5, 0.3), (32.5, 16.5, 0.6), (0.5, 16.5, 0.2)],        # shares it (counter-clockwise)
+        [(16.5, 32.5, 0.4), (47.5, 32.5, 0.4), (16.5, 35.5, 0.4)],      # edges on tile rows / columns
+        [(1.5, 20.5, 0.9), (62.5, 22.5, 0.1), (62.5, 22.75, 0.5)],      # sliver across 4 tile columns
+        [(3.5, 60.5, 0.6), (60.5, 40.5, 0.3), (60.75, 40.5, 0.3)],      # diagonal sliver
+        [(32.5, 48.5, 0.5), (20.5, 60.5, 0.5), (20.5, 48.5, 0.5)],      # corner texel on two edges
+        [(47.5, 51.5, 0.7), (63.5, 51.5, 0.7), (47.5, 63.5, 0.7)],      # vertex at a tile's corner texel
+        [(10.0, 40.0, 0.45), (30.0, 44.0, 0.35), (12.0, 58.0, 0.55)],   # generic, off the texel grid
+    ]
+    tris = np.array(T, np.float32)
+    e1 = tris[:, 1].astype(np.float64) - tris[:, 0]
+    e2 = tris[:, 2].astype(np.float64) - tris[:, 0]
+    nrm = np.cross(e1, e2)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    sc = S.Scene(tris=tris, normals=nrm.astype(np.float32))
+    base = S.make_frame(S.make_scene("tiny", 0), 48, 40, 64, light_pos=(0.0, 3.0, 0.0), eye=(3.0, 1.5, 0.0))
+    fr = dataclasses.replace(base, m_light=_ortho(64, 64), m_cam=_ortho(48, 40))
+    ref_sm = oracle.raster(sc.tris, fr.m_light, 64, 64, "depth")[0]
+    ref_key = oracle.raster(sc.tris, fr.m_cam, 48, 40, "key")[0]
+    got = _to_np(_builder(sc)(fr))
+    covered = int((ref_sm != 0x7F800000).sum())
+    seen = int((ref_key != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+    print(f"[tiles/ties] covered texels {covered}, camera pixels {seen}", flush=True)
+    assert covered > 500 and seen > 500
+    np.testing.assert_array_equal(got["sm"], ref_sm)
+    np.testing.assert_array_equal(got["gbuf"], ref_key)
