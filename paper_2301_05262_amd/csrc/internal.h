@@ -63,6 +63,9 @@ struct GatherParams {
     int S;
     float E[3], fwd[3], right[3], up[3];
     float tanx, tany, fc;
+    // filled by gather(): per-launch constants of the per-pixel arithmetic
+    float tau;                // (2 tanl) / S, float32
+    double rw, rh;            // 1 / w and 1 / h, float64, rounded to nearest
 };
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
                   const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,

@@ -541,9 +541,16 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
     for (int k = 0; k < PX; ++k) {
         const int i = ib + 256 * k;
         tt[k] = 0.0;
-        // receiver: the pixel-centre camera ray meets the triangle's plane (float64)
-        const double ndcx = (2.0 * ((double)i + 0.5)) / (double)w - 1.0;
-        const double ndcy = (2.0 * ((double)j + 0.5)) / (double)h - 1.0;
+        // receiver: the pixel-centre camera ray meets the triangle's plane
+        // (float64).  The quotients (2 i + 1) / w and (2 j + 1) / h are the
+        // correctly rounded ones, from the rounded reciprocal and one
+        // Markstein correction (Markstein's theorem; the operands are positive
+        // integers below 2^15, and every pair up to 16384 was checked against
+        // the IEEE division).
+        const double ax2 = 2.0 * ((double)i + 0.5), ay2 = 2.0 * ((double)j + 0.5);
+        const double qx0 = ax2 * P.rw, qy0 = ay2 * P.rh;
+        const double ndcx = fma(fma(-qx0, (double)w, ax2), P.rw, qx0) - 1.0;
+        const double ndcy = fma(fma(-qy0, (double)h, ay2), P.rh, qy0) - 1.0;
         const double ax = ndcx * (double)P.tanx, ay = ndcy * (double)P.tany;
 #pragma unroll
         for (int d = 0; d < 3; ++d) D[k][d] = ((double)P.fwd[d] + ax * (double)P.right[d]) + ay * (double)P.up[d];
@@ -604,7 +611,7 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                 else z = lin_depth(__uint_as_float(tex[k]), P.nl, P.fl);
             }
             // slope-scaled depth bias from the angle between normal and light direction
-            const float tau = (2.0f * P.tanl) / (float)P.S;
+            const float tau = P.tau;
             const float lx = P.L[0] - Pw[k][0], ly = P.L[1] - Pw[k][1], lz = P.L[2] - Pw[k][2];
             float ll = lx * lx + ly * ly;
             ll = ll + lz * lz;
@@ -720,9 +727,13 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     return hipGetLastError();
 }
 
-hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
+hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& params,
                   const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s) {
+    GatherParams p = params;
+    p.tau = (2.0f * p.tanl) / (float)p.S;
+    p.rw = 1.0 / (double)w;
+    p.rh = 1.0 / (double)h;
     dim3 grid((w + 256 * kGatherPx - 1) / (256 * kGatherPx), h);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
     TraceScope ts("gather", fs == 1 ? " soft8" : (fs == 2 ? " paper4" : " hard6"), s);
