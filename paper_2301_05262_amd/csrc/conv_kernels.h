@@ -184,6 +184,17 @@ __device__ __forceinline__ void unpack_block(const u32x4& r, float* v) {
 // or store whose scalar part is a compile-time constant costs no vector ALU
 // for its address.  Reads past the range return zero.
 constexpr int kBufWord3 = 0x00020000;   // raw 32-bit data format
+// v summed over the wave's four 16-lane rows: every lane gets
+// (v_r0 + v_r1) + (v_r2 + v_r3) of its position within the row (the same
+// values as v + xor-16 shuffle, then + xor-32 shuffle, by commutativity),
+// from two VALU row swaps instead of two LDS permutes.
+__device__ __forceinline__ float sum_rows4(float v) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, kBufWord3);
 }
@@ -674,8 +685,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int x0, int y0, int
             for (int f = 0; f < NF; ++f)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) s += hw[f][e] * acc[m][f][e];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
+            s = sum_rows4(s);
             if (ok && g == 0) {
                 const float logit = s + hb;
                 a.vis[p] = 1.0f / (1.0f + __expf(-logit));

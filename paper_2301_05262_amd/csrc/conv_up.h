@@ -310,8 +310,7 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v += hw[f][e] * acc[m][p][f][e];
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
+                v = sum_rows4(v);
                 s[m][p] = v + hb;
             }
         // lane group g finishes rows m with m % 4 == g: one sigmoid per pixel

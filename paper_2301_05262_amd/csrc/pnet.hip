@@ -173,8 +173,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
             for (int f2 = 0; f2 < NF2; ++f2)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) s += hw[f2][e] * acc2[m][f2][e];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
+            s = sum_rows4(s);
             if (y < h && x < w && g == 0) {
                 const size_t p = ((size_t)n * h + y) * w + x;
                 const float logit = s + hb;
@@ -208,8 +207,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
                 for (int f2 = 0; f2 < NF2; ++f2)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) t += hw[k][f2][e] * acc2[m][f2][e];
-                t += __shfl_xor(t, 16);
-                t += __shfl_xor(t, 32);
+                t = sum_rows4(t);
                 s[k] = t;
             }
             const float mine = g == 0 ? s[0] : (g == 1 ? s[1] : (g == 2 ? s[2] : s[3]));
