@@ -65,7 +65,8 @@ def _check(desc, flat, feat, label):
         assert np.all(np.abs(pre[bad] - mid) <= 1e-5 * np.abs(mid))
 
 
-@pytest.mark.parametrize("desc,shape", [(S.U2, (1, 64, 64)), (S.U3, (2, 72, 200)), (S.U3, (1, 4, 4))])
+@pytest.mark.parametrize("desc,shape", [(S.U2, (1, 64, 64)), (S.U3, (2, 72, 200)), (S.U3, (1, 4, 4)),
+                                        (S.U3, (1, 20, 16384)), (S.U3, (1, 16384, 20))])
 def test_f8_forward_random_features(desc, shape):
     n, h, w = shape
     flat = S.he_weights(desc, 51, bias_scale=0.1)
