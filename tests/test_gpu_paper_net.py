@@ -43,9 +43,11 @@ def _run(m, feat):
 
 
 @pytest.mark.parametrize("widths,shape", [(P3, (2, 64, 96)), (P3, (1, 36, 52)), (P5, (2, 64, 96)),
-                                          (P5, (1, 48, 80))])
+                                          (P5, (1, 48, 80)), (P5, (1, 16, 16384)), (P5, (1, 16384, 16))])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_paper_net_random(widths, shape, dtype):
+    # the last two: the ABI's maximum extent, with one row (column) of
+    # pixels at the 5-level net's bottleneck
     n, h, w = shape
     flat = _weights(widths, 41)
     feat = S.SplitMix64(42).uniforms(n * h * w * 4, -1, 1).reshape(n, h, w, 4).astype(np.float32)
