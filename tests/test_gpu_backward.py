@@ -76,6 +76,96 @@ def test_backward_matches_oracle(desc, shape):
     np.testing.assert_allclose(acc.cpu().numpy(), 2 * dw.astype(np.float32), rtol=1e-6, atol=0)
 
 
+# A ReLU mask or a max-pool route is fixed at float32 only where the decision
+# is further from a tie than float32 rounding of the pre-activation.  The bound
+# used: |z| (or the gap between a window's maximum and another window value)
+# at most EPS_TIE * sum |w| |x| + |b| over the conv that produced it, about
+# 170 float32 ulps of the absolute sum.
+EPS_TIE = 1e-5
+# Level-0 pixels beyond its own footprint from which the visibility gradient
+# reaches a decision (the head is 1x1; each conv adjoint spreads one pixel of
+# its level, each upsampling adjoint taps [2p-1, 2p+2]): D0 0, D1 2, B 6,
+# E1 14 (skip 4, through the pool 14), E0 17 (skip 1, through the pool 17),
+# the routes of the E1 and E0 pools 10 and 16.  Used with a margin.
+REACH = {"D0": 1, "D1": 4, "B": 8, "E1": 16, "E0": 20, "pool1": 12, "pool0": 18}
+
+
+def _clear_windows(desc, flat, feat, axis, length=8, count=8):
+    """Windows along the long image axis (1 = rows, 2 = columns) whose level-0
+    extent no near-tie decision of the float64 forward can reach: there the
+    float32 forward takes every decision the oracle takes."""
+    act = onet.forward(desc.c_in, desc.widths, flat, feat)
+    P = onet.split_params(desc.c_in, desc.widths, flat)
+    L = len(desc.widths)
+    size = feat.shape[axis]
+    blocked = np.zeros(size + 1, np.int64)
+
+    def block(coords, level, reach):
+        lo = np.clip(coords * (1 << level) - reach, 0, size)
+        hi = np.clip((coords + 1) * (1 << level) + reach, 0, size)
+        np.add.at(blocked, lo, 1)
+        np.add.at(blocked, hi, -1)
+
+    inputs = {"E0": act["x"], "B": act[f"p_E{L - 2}"]}
+    for l in range(1, L - 1):
+        inputs[f"E{l}"] = act[f"p_E{l - 1}"]
+    for l in range(L - 1):
+        inputs[f"D{l}"] = np.concatenate([act[f"a_E{l}"], act[f"up_D{l}"]], -1)
+    level = {"B": L - 1, **{f"E{l}": l for l in range(L - 1)}, **{f"D{l}": l for l in range(L - 1)}}
+    for name, x in inputs.items():
+        w, b = P[name]
+        A = onet.conv3x3(np.abs(x), np.abs(w), np.abs(b))
+        near = np.abs(act["z_" + name]) <= EPS_TIE * A
+        pos = np.nonzero(near.any(axis=(0, 3 - axis, 3)))[0]
+        block(pos, level[name], REACH[name])
+        if name.startswith("E"):
+            n, h, w_, c = A.shape
+            win = lambda t: t.reshape(n, h // 2, 2, w_ // 2, 2, c).transpose(0, 1, 3, 2, 4, 5).reshape(
+                n, h // 2, w_ // 2, 4, c)
+            a, s = win(act["a_" + name]), win(A)
+            top = a.max(axis=3, keepdims=True)
+            close = (top - a <= EPS_TIE * s) & (a < top) & (top > 0)
+            pos = np.nonzero(close.any(axis=3).any(axis=(0, 3 - axis, 3)))[0]
+            block(pos, level[name] + 1, REACH["pool" + name[1:]])
+    free = np.cumsum(blocked)[:size] == 0
+    runs = np.convolve(free.astype(np.int64), np.ones(length, np.int64), "valid") == length
+    starts = np.nonzero(runs)[0]
+    picked = sorted({int(starts[np.abs(starts - t).argmin()]) for t in np.linspace(0, size - length, count)})
+    return picked, act
+
+
+@pytest.mark.parametrize("shape", [(1, 20, 16384), (1, 16384, 20)])
+def test_backward_maximum_extent(shape):
+    """The longest image side the library takes (16384), 20 pixels across.
+    Over a third of a million pixels some hundreds of ReLU and max-pool
+    decisions sit within float32 rounding of a tie, and flipping one moves a
+    whole gradient; the visibility gradient is therefore non-zero only on
+    8-pixel windows that no such decision reaches (chosen on the float64
+    oracle alone), the first and last reachable ones included.  The whole
+    extent is still processed: dW and dfeat (zero outside the windows' cones,
+    exactly) are compared element-wise at the usual tolerance."""
+    desc = S.U3
+    n, h, w = shape
+    axis = 2 if w > h else 1
+    flat = S.he_weights(desc, 21, bias_scale=0.1)
+    feat = _rand((n, h, w, desc.c_in), 22)
+    starts, _ = _clear_windows(desc, flat, feat, axis)
+    size = shape[axis]
+    assert len(starts) >= 4 and starts[0] < 512 and starts[-1] > size - 512, starts
+    keep = np.zeros(size, bool)
+    for s0 in starts:
+        keep[s0:s0 + 8] = True
+    mask = keep[None, None, :] if axis == 2 else keep[None, :, None]
+    dvis = (_rand((n, h, w), 23) * mask).astype(np.float32)
+    ref_w, ref_f = onet.backward(desc.c_in, desc.widths, flat, feat, dvis)
+    dw, df = _gpu_grads(_net(desc, flat), feat, dvis)
+    per = _stage_errors(desc, dw, ref_w)
+    e_f = np.abs(df - ref_f).max() / np.abs(ref_f).max()
+    print(f"[{shape}] windows {starts}  dW per-stage rel err {per}  dfeat {e_f:.3e}", flush=True)
+    assert max(per.values()) <= REL and e_f <= REL
+    assert np.all(df[ref_f == 0] == 0)
+
+
 def test_backward_on_soft_shadow_features():
     """Rendered soft-shadow features are smooth, so thousands of 2x2 pooling
     windows hold two values that differ by less than float32 accumulation
