@@ -3,9 +3,17 @@
 One step = the whole inference path for one 1920x1080 frame of the
 19,632-triangle synthetic scene with a 2048^2 shadow map: light-view
 z-buffer, camera G-buffer, feature gather (HARD6) and the U-Net forward
-(U3: widths 16/32/64).  `value` is the BF16 form's ms/frame; the FP32 and
-FP16 forms are timed the same way and reported beside it, each with its
+(U3: widths 16/32/64).  `value` is the BF16 form's ms/frame for that whole
+step; the network alone (nsm_forward, the paper's convention, which leaves
+out the G-buffer) is `network_ms` beside it.  The FP32, FP16 and 8-bit
+storage forms are timed the same way and reported beside it, each with its
 visibility error against the FP64 oracle.
+
+Rooflines: `roofline` is the dominant kernel of the BF16 step;
+`roofline_classes` gives each layer class's fraction (raster + gather and
+the BF16 thin convs against HBM, BF16 D1 against the BF16 MFMA peak, the
+FP32 convs against the FP32 MFMA peak), each from algorithmic bytes or
+FLOPs over the summed kernel times of the class.
 
 Timing: W untimed warm-up steps, then K steps bracketed by
 torch.cuda.synchronize() with events on the launch stream (the library
@@ -41,8 +49,8 @@ KERNEL_SYMBOL = {
     "conv3x3 6+0->16 Pool bf16": "k_conv3x3<bf16, true, 6, 0, 16, Pool, 8>",
     "conv3x3 16+0->32 Pool bf16": "k_conv3x3<bf16, false, 16, 0, 32, Pool, 8>",
     "conv3x3 32+0->64 Store bf16": "k_conv3x3<bf16, false, 32, 0, 64, Store, 8>",
-    "conv3x3 32+64->32 Store phase bf16": "k_conv3x3_up<bf16, 32, 64, 32, Store, 16, 4>",
-    "conv3x3 16+32->16 Head phase bf16": "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 8>",
+    "conv3x3 32+64->32 Store phase bf16": "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>",
+    "conv3x3 16+32->16 Head phase bf16": "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 4>",
 }
 
 
@@ -103,10 +111,49 @@ def _base(name):
 
 def raster_costs(n_tris, h, w, sm):
     """Algorithmic HBM bytes of the fused light + camera z-buffer: each target
-    read and written once (u32 shadow map, u64 camera keys) plus one 64-byte
-    setup record per triangle and pass."""
-    tgt = sm * sm * 4 + h * w * 8
-    return {"raster light+camera": (0.0, 2.0 * tgt + 2 * n_tris * 64)}
+    written once (u32 shadow map, u64 camera keys) and the triangles' 36-byte
+    vertex triples read once per pass."""
+    return {"raster light+camera": (0.0, float(sm * sm * 4 + h * w * 8 + 2 * n_tris * 36))}
+
+
+def gather_costs(n_tris, h, w, channels, name):
+    """Algorithmic HBM bytes of the feature gather: per pixel the 8-byte camera
+    key, the 4-byte map texel, the float32 channels and the mask byte; per
+    triangle its vertices and normal (48 bytes), read once."""
+    return {name: (0.0, float(h * w * (8 + 4 + 4 * channels + 1) + n_tris * 48))}
+
+
+def class_rooflines(results, costs_of, forms):
+    """Fraction of the relevant peak per layer class, from algorithmic work over
+    the summed per-kernel times of the class (one frame per launch)."""
+    out = {}
+
+    def frac(form, keys, kind, peak):
+        ks = results[form]["kernels"]
+        c = costs_of(form)
+        t = sum(ks[k]["avg_us"] for k in keys if k in ks) * 1e-6
+        work = sum(c[_base(k)][0 if kind == "flops" else 1] for k in keys if k in ks and _base(k) in c)
+        if t <= 0:
+            return None
+        unit = "TFLOP/s" if kind == "flops" else "GB/s"
+        achieved = work / t / (1e12 if kind == "flops" else 1e9)
+        return {"kernels": [k for k in keys if k in ks], "us": t * 1e6, "achieved": achieved,
+                "peak": peak / (1e12 if kind == "flops" else 1e9), "unit": unit, "frac": work / t / peak}
+
+    for form in forms:
+        ks = list(results[form]["kernels"])
+        feat = [k for k in ks if k.split(" ")[0] in ("setup+clear", "tile_scan", "raster", "gather")]
+        convs = [k for k in ks if k.startswith("conv3x3")]
+        d1 = [k for k in convs if "+64->32" in k]
+        thin = [k for k in convs if k not in d1]
+        if form == forms[0]:
+            out["raster+gather (hbm)"] = frac(form, feat, "bytes", HBM_PEAK)
+        if form == "f32":
+            out["fp32 convs (fp32 mfma)"] = frac(form, convs, "flops", MFMA_PEAK["f32"])
+        elif form in ("bf16", "f16", "f8"):
+            out[f"{form} thin convs E0,E1,B,D0 (hbm)"] = frac(form, thin, "bytes", HBM_PEAK)
+            out[f"{form} D1 (mfma)"] = frac(form, d1, "flops", MFMA_PEAK[form])
+    return out
 
 
 def batched_section(S, torch, seed, reps):
@@ -343,6 +390,63 @@ def paper_net_section(S, torch, seed, steps):
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, fr, desc, flat, band_rows=272, reps=3):
+    """The CPU oracle per stage, median of `reps` runs, at all threads the
+    process may use and at one thread: the C rasteriser (light map and camera
+    keys) and the C gather on the whole frame, the float64 U-Net forward on a
+    band of `band_rows` full-width rows of the frame's features, scaled to the
+    frame by its pixel count (its cost is linear in pixels)."""
+    import threadpoolctl
+
+    import oracle
+    from oracle import net as onet
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
+    H, W = fr.height, fr.width
+
+    def stages(nt):
+        med = {}
+        with threadpoolctl.threadpool_limits(nt):
+            runs = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                sm, _ = oracle.raster(scene.tris, fr.m_light, fr.sm_size, fr.sm_size, "depth")
+                t1 = time.perf_counter()
+                gb, _ = oracle.raster(scene.tris, fr.m_cam, W, H, "key")
+                t2 = time.perf_counter()
+                ofe = oracle.gather(scene, fr, gb, sm)
+                t3 = time.perf_counter()
+                band = ofe["feat"][None, :band_rows]
+                onet.forward(desc.c_in, desc.widths, flat, band, keep=False)
+                t4 = time.perf_counter()
+                runs.append((t1 - t0, t2 - t1, t3 - t2, (t4 - t3) * H / band_rows))
+            r = np.median(np.array(runs), axis=0) * 1e3
+            med = {"light_zbuffer_ms": r[0], "camera_gbuffer_ms": r[1], "gather_ms": r[2], "forward_ms": r[3]}
+        med = {k: float(v) for k, v in med.items()}
+        med["ms_per_frame"] = sum(med.values())
+        ofe.update(sm=sm, gbuf=gb)
+        return med, ofe
+
+    many, ofe = stages(threads)
+    one, _ = stages(1)
+    return ({"value": many["ms_per_frame"], "unit": "ms/frame", "cores": threads, "kind": "oracle",
+             "sample": (f"one 1920x1080 frame: C rasteriser (2048^2 light map + camera keys) and C gather "
+                        f"on the whole frame, numpy float64 U-Net forward on a {band_rows}-row full-width "
+                        f"band scaled by {H}/{band_rows}; median of {reps} runs per stage"),
+             "stages": many, "one_thread": one, "cpu_model": _cpu_model(), "nproc": os.cpu_count()},
+            ofe)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -416,23 +520,11 @@ def main():
     # visibility error of each form against the FP64 oracle (and the CPU baseline timing)
     cpu = None
     if args.cpu_sample == "frame":
-        import oracle
         from oracle import net as onet
-        t0 = time.perf_counter()
-        ofe = oracle.build_features(scene, fr)
+        cpu, ofe = cpu_baseline(scene, fr, desc, flat)
+        print(f"[bench] cpu oracle: {cpu['value']:.0f} ms/frame at {cpu['cores']} threads, "
+              f"{cpu['one_thread']['ms_per_frame']:.0f} ms/frame at 1", file=sys.stderr, flush=True)
         ref = onet.forward(desc.c_in, desc.widths, flat, ofe["feat"][None], keep=False)
-        t1 = time.perf_counter()
-        threads = os.cpu_count() or 1
-        try:
-            import threadpoolctl
-            info = threadpoolctl.threadpool_info()
-            threads = max([threads if "OMP_NUM_THREADS" not in os.environ else int(os.environ["OMP_NUM_THREADS"])]
-                          + [int(i.get("num_threads", 1)) for i in info])
-        except Exception:
-            pass
-        cpu = {"value": 1e3 * (t1 - t0), "unit": "ms/frame", "cores": threads, "kind": "oracle",
-               "sample": "one full 1920x1080 frame: C rasteriser (2048^2 map + camera), C gather, "
-                         "numpy float64 U-Net forward"}
         for f in forms:
             v = vis[f].cpu().numpy()[0].astype(np.float64)
             d = np.abs(v - ref["vis"][0])
@@ -441,15 +533,19 @@ def main():
 
     # roofline of the dominant kernel of the headline (BF16) form
     head = "bf16" if "bf16" in forms else forms[0]
-    costs = stage_costs(desc.widths, desc.c_in, H, W, head)
-    costs.update(raster_costs(scene.n_tris, H, W, fr.sm_size))
+    def costs_of(form):
+        c = stage_costs(desc.widths, desc.c_in, H, W, form)
+        c.update(raster_costs(scene.n_tris, H, W, fr.sm_size))
+        c.update(gather_costs(scene.n_tris, H, W, desc.c_in, "gather hard6"))
+        return c
+
+    costs = costs_of(head)
     kern = results[head]["kernels"]
     dom = max(kern, key=lambda k: kern[k]["avg_us"])
     base = _base(dom)
     roof = None
     for f in forms:
-        c = stage_costs(desc.widths, desc.c_in, H, W, f)
-        c.update(raster_costs(scene.n_tris, H, W, fr.sm_size))
+        c = costs_of(f)
         for k, v in results[f]["kernels"].items():
             b = _base(k)
             if b in c:
@@ -475,6 +571,7 @@ def main():
         measured = recorded_traffic(TRAFFIC_MD).get(KERNEL_SYMBOL.get(dom, ""), None) if head == "bf16" else None
         roof.update({"traffic": measured, "avg_us": kern[dom]["avg_us"], "algorithmic_bytes": by,
                      "algorithmic_flops": fl})
+    roof_classes = class_rooflines(results, costs_of, [head] + [f for f in forms if f != head])
     batched = None
     if args.batched:
         batched = batched_section(S, torch, args.seed, reps=20)
@@ -508,7 +605,9 @@ def main():
         "config": {"workload": WORKLOAD, "width": W, "height": H, "sm_size": fr.sm_size,
                    "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
                    "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
-        "forms": results, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "network_ms": results[head]["network_ms"],
+        "forms": results, "roofline": roof, "roofline_classes": roof_classes, "cpu_baseline": cpu,
+        "batched": batched,
         "paper_net": paper_net, "training": training, "temporal": temporal,
     }
     print(json.dumps(line))

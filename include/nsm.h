@@ -28,9 +28,19 @@
  *   - All arguments are validated before anything is launched; a non-OK
  *     status means nothing was enqueued.  Faults inside kernels surface at
  *     the caller's next synchronisation.  No C++ exception crosses the ABI.
+ *   - Debug mode: with the environment variable NSM_DEBUG_SYNC=1 (read at
+ *     every call), each call synchronises its stream after every kernel it
+ *     launches and returns NSM_E_LAUNCH if the launch or the kernel failed,
+ *     so a fault is reported by the call that caused it.  Results are the
+ *     same bits as without it; only the calls become blocking.
  *   - Images are row-major with row 0 at the bottom (ndc y = -1) and the
  *     column index growing with ndc x; tensors are NHWC.
- *   - A context is not internally synchronised: use one per stream.
+ *   - A context is not internally synchronised: use one per stream.  Its
+ *     packed weights are read by every nsm_forward / nsm_backward, so a
+ *     nsm_set_weights on one stream must be ordered (events) against calls
+ *     on other streams that use the same context; likewise a workspace
+ *     must not be shared by calls that may run concurrently.
+ *   - Triangle counts are at most 2^28 (NSM_E_SHAPE above).
  */
 #ifndef NSM_H
 #define NSM_H
@@ -208,13 +218,30 @@ nsm_status nsm_workspace_bytes(const nsm_ctx *ctx, int n, int h, int w, int trai
  *   feat       [n][h][w][c_in] float32.
  *   vis_out    [n][h][w] float32 in (0, 1).
  *   logits_out [n][h][w] float32 pre-sigmoid values, or NULL.
- * h and w must be divisible by 2^(levels-1). */
+ * h and w must be divisible by 2^(levels-1).
+ * On return (once the stream has run) the workspace holds the stored
+ * activations of NSM_ARCH_UNET, in the context's storage type (float32,
+ * bfloat16, float16, or E4M3 bytes for NSM_F8), NHWC over the n frames, each
+ * tensor starting at a multiple of 256 bytes right after the previous one:
+ * for l = 0 .. L-2 the encoder output e_l (h_l x w_l x widths[l], post-ReLU)
+ * then its 2x2 max-pool p_l; the bottleneck output b; the decoder outputs
+ * d_l for l = 1 .. L-2 (h_l = h >> l).  The level-0 decoder output feeds the
+ * head in float32 registers and is not stored.  This layout lets a caller
+ * inspect intermediate tensors; it is fixed for a given ABI version. */
 nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
                        float *logits_out, void *workspace, size_t ws_bytes, void *stream);
 
-/* nsm_backward -- gradient of sum(dvis * vis) (FP32 NSM_ARCH_UNET contexts).
+/* nsm_backward -- gradient of sum(dvis * vis) (FP32 NSM_ARCH_UNET contexts):
+ * the network's training pass (paper Sec. 3.3 trains the network on
+ * per-pixel losses against ray-traced targets; supplemental Sec. 5 on the
+ * temporal windows), so dvis is the loss gradient with respect to the
+ * visibility (e.g. 2 (vis - target) / (n h w) for the mean squared error).
  * Recomputes the forward activations into the workspace, then applies the
- * adjoint of every stage.
+ * adjoint of every stage: the sigmoid and 1x1 head, each 3x3 convolution
+ * (input gradient by the flipped kernel, weight gradient as a sum over
+ * pixels), ReLU (gradient where the pre-activation is > 0), the concat
+ * split, the bilinear upsampling's transpose and the max-pool routing to
+ * the first maximum of each window in (0,0), (0,1), (1,0), (1,1) order.
  *   dvis       [n][h][w] float32 upstream gradient.
  *   dw_out     [n_params] float32 in the flat parameter order; overwritten,
  *              or added to when accumulate != 0.
@@ -248,6 +275,7 @@ nsm_status nsm_perturbation_loss_workspace_bytes(int n, int p, int h, int w, siz
 nsm_status nsm_perturbation_loss(const float *vis, const float *target, int n, int p, int h, int w,
                                  float alpha, double *loss_out, float *dvis0_out, void *workspace,
                                  size_t ws_bytes, void *stream);
+
 
 /* nsm_temporal_instability -- one frame pair of the temporal-instability
  * metric of paper Sec. 3.4, Eq. 3:

@@ -26,12 +26,15 @@ max-pool routes each window's gradient to the first maximum in the order
 (0,0), (0,1), (1,0), (1,1); the upsampling adjoint is the transpose of the
 interpolation (scatter-add with the same weights); concat splits channels.
 
-Low-precision emulation: the same forward with round-to-nearest-even to the
-storage type (bfloat16 or float16) applied exactly where the GPU stores a
-value in that type (features on load, 3x3 weights, every stored activation
-and the upsampled operand), accumulating in float64.  The 1x1 head keeps
-float32 weights and reads the unrounded last activation.  The 8-bit storage
-form rounds stored activations to FP8 E4M3 and the rest to bfloat16.
+Low-precision model (the precision form, Sec. 3.5 runs the network in half
+precision): the same forward with round-to-nearest-even applied exactly
+where the GPU path holds a value in a narrower type -- features on load,
+3x3 weights, every stored activation; in the decoders, the upsampled tensor
+on border pixels and the four phase kernels (bilinear x2 folded into the
+3x3 weights, formed in float64 and rounded once) on interior pixels --
+accumulating in float64.  The 1x1 head keeps float32 weights and reads the
+unrounded last activation.  The 8-bit storage form rounds stored
+activations to FP8 E4M3 and the rest to bfloat16.
 """
 import numpy as np
 
@@ -267,35 +270,183 @@ def round_e4m3(x):
     return np.where(x < 0, -q, q)
 
 
-def forward_lowp(c_in, widths, flat, feat, dtype):
-    """Forward with storage rounding emulated at the GPU's store points.
+# Rounding points of the precision forms, one helper each, so that every
+# point is a single place (and a test can move any one of them).  `cmp` rounds
+# to the compute type the MFMAs read (bfloat16 or float16; bfloat16 in the
+# 8-bit storage form), `st` to the storage type of activations in memory.
+def _round_features(x, cmp):
+    return cmp(x)
 
-    dtype 'f8' is 8-bit temporary storage: activations are stored as E4M3,
-    while features on load, weights and the upsampled operand are bfloat16
-    (the compute type)."""
-    rnd = {"bf16": round_bf16, "f16": round_f16, "f8": round_bf16}[dtype]
-    st = round_e4m3 if dtype == "f8" else rnd
+
+def _round_weights(w, cmp):
+    return cmp(w)
+
+
+def _round_bias(b):
+    return b                       # biases stay float32
+
+
+def _store(a, st):
+    return st(a)
+
+
+def _store_pool(a, st):
+    return st(maxpool2(a))
+
+
+def _phase_up(low, w_up, cmp):
+    """Interior decoder pixels: the phase kernels of the float weights,
+    formed in float64 and rounded once (via float32) to the compute type,
+    applied to the stored low-resolution tensor."""
+    return phase_conv(low, cmp(phase_kernels(w_up)))
+
+
+def _border_up(low, cmp):
+    """Border decoder pixels: the upsampled tensor, rounded to the compute
+    type, feeds the plain 3x3 conv."""
+    return cmp(upsample2(low))
+
+
+def _head_input(a):
+    return a                       # the last activation stays float32
+
+
+def _head_weights(w):
+    return w                       # head weights stay float32
+
+
+def _lowp_types(dtype):
+    cmp = {"bf16": round_bf16, "f16": round_f16, "f8": round_bf16}[dtype]
+    st = round_e4m3 if dtype == "f8" else cmp
+    return cmp, st
+
+
+def up_coupling():
+    """C[p, k, t]: weight of low-resolution row i - 1 + t in row 2i + p + k - 1
+    of the bilinear x2 upsampling, away from the border (read off the taps of
+    upsample2 at an interior row)."""
+    n_low, i = 8, 4
+    r0, r1, w0, w1 = _interp_taps(2 * n_low, n_low)
+    C = np.zeros((2, 3, 3))
+    for p in range(2):
+        for k in range(3):
+            u = 2 * i + p + k - 1
+            C[p, k, r0[u] - (i - 1)] += w0[u]
+            C[p, k, r1[u] - (i - 1)] += w1[u]
+    return C
+
+
+def phase_kernels(w_up):
+    """Bilinear x2 followed by a 3x3 conv is linear in the low-resolution
+    input, so away from the border it is a 3x3 conv over the low-resolution
+    image with one kernel per output phase (y mod 2, x mod 2):
+        Wp[py, px, o, t, u, c] = sum_{ky, kx} C[py, ky, t] C[px, kx, u] W[o, ky, kx, c].
+    w_up [Co, 3, 3, Cu] -> Wp [2, 2, Co, 3, 3, Cu] (float64)."""
+    C = up_coupling()
+    return np.einsum("pkt,qlu,oklc->pqotuc", C, C, np.asarray(w_up, np.float64))
+
+
+def phase_conv(low, Wp):
+    """out[n, 2i + py, 2j + px, o] = sum_{t, u, c} Wp[py, px, o, t, u, c]
+    * low[n, i - 1 + t, j - 1 + u, c], low taps clamped to the image (the
+    clamp of the bilinear interpolation).  Equals conv3x3(upsample2(low), W)
+    except on the first and last output rows and columns, where the conv's
+    zero padding of the upsampled image is not a clamp."""
+    n, hl, wl, _ = low.shape
+    lp = np.pad(np.asarray(low, np.float64), ((0, 0), (1, 1), (1, 1), (0, 0)), mode="edge")
+    co = Wp.shape[2]
+    out = np.zeros((n, 2 * hl, 2 * wl, co))
+    for py in range(2):
+        for px in range(2):
+            acc = np.zeros((n, hl, wl, co))
+            for t in range(3):
+                for u in range(3):
+                    acc += lp[:, t:t + hl, u:u + wl, :] @ Wp[py, px, :, t, u, :].T
+            out[:, py::2, px::2, :] = acc
+    return out
+
+
+def lowp_encoder_pre(x, w, b, cmp, magnitude=False):
+    """Pre-activation of an encoder / bottleneck stage of the precision form
+    from its stored input x; with magnitude=True the same sum over absolute
+    values of every term (the scale of its float32 rounding error)."""
+    wq, bq = _round_weights(w, cmp), _round_bias(b)
+    if magnitude:
+        return conv3x3(np.abs(x), np.abs(wq), np.abs(bq))
+    return conv3x3(x, wq, bq)
+
+
+def lowp_decoder_pre(skip, low, w, b, cmp, box=None, magnitude=False):
+    """Pre-activation of a decoder stage (concat [skip, up(low)] -> 3x3) of the
+    precision form from its stored inputs.  Output pixels inside `box`
+    (r0, r1, c0, c1) take the phase form (phase kernels rounded once, applied
+    to `low`); the others the general form (rounded weights on the rounded
+    upsampled tensor).  magnitude=True: the sum over absolute values."""
+    cs = skip.shape[-1]
+    wq, bq = _round_weights(w, cmp), _round_bias(b)
+    f = np.abs if magnitude else (lambda v: v)
+    u = _border_up(low, cmp)
+    z = conv3x3(f(np.concatenate([skip, u], axis=-1)), f(wq), f(bq))
+    if box is not None:
+        r0, r1, c0, c1 = box
+        zs = conv3x3(f(skip), f(wq[..., :cs]), f(bq))
+        if magnitude:
+            zp = zs + phase_conv(np.abs(low), np.abs(cmp(phase_kernels(w[..., cs:]))))
+        else:
+            zp = zs + _phase_up(low, w[..., cs:], cmp)
+        z[:, r0:r1, c0:c1] = zp[:, r0:r1, c0:c1]
+    return z
+
+
+def forward_lowp(c_in, widths, flat, feat, dtype, phase=None, keep=False):
+    """Forward of the precision form with storage rounding at the GPU's store
+    points (a bit model up to float32 accumulation order):
+
+      features   rounded to the compute type on load;
+      3x3 weights rounded to the compute type; biases float32;
+      e_l, p_l   encoder outputs and their 2x2 max-pools, stored;
+      b, d_l     bottleneck and decoder outputs (l >= 1), stored;
+      decoders   interior pixels (phase[name] = (r0, r1, c0, c1) in the
+                 stage's output pixels): the four phase kernels of the float
+                 weights, formed in float64 and rounded once, applied to the
+                 stored low-resolution tensor; other pixels: rounded weights
+                 on the upsampled tensor rounded to the compute type;
+      head       1x1 with float32 weights on the unrounded (float32) last
+                 decoder activation, then the sigmoid.
+
+    dtype 'bf16' / 'f16': compute and storage type alike; 'f8': storage E4M3,
+    compute bfloat16.  Sums are float64.  phase=None computes every decoder
+    pixel in the general form.  keep=True also returns every stored tensor."""
+    cmp, st = _lowp_types(dtype)
+    phase = phase or {}
     P = split_params(c_in, widths, flat)
-    Pq = {k: (rnd(w), b) for k, (w, b) in P.items()}
-    Pq["H"] = P["H"]
     L = len(widths)
-    x = rnd(np.asarray(feat, np.float64))
+    x = _round_features(np.asarray(feat, np.float64), cmp)
     if x.ndim == 3:
         x = x[None]
+    out = {}
     cur = x
     skips = []
     for l in range(L - 1):
-        a = relu(conv3x3(cur, *Pq[f"E{l}"]))
-        skips.append(st(a))
-        cur = st(maxpool2(a))
-    cur = st(relu(conv3x3(cur, *Pq["B"])))
+        a = relu(lowp_encoder_pre(cur, *P[f"E{l}"], cmp))
+        skips.append(_store(a, st))
+        cur = _store_pool(a, st)
+        out[f"e{l}"], out[f"p{l}"] = skips[-1], cur
+    cur = _store(relu(lowp_encoder_pre(cur, *P["B"], cmp)), st)
+    out["b"] = cur
     for l in range(L - 2, -1, -1):
-        u = rnd(upsample2(cur))
-        a = relu(conv3x3(np.concatenate([skips[l], u], axis=-1), *Pq[f"D{l}"]))
-        cur = a if l == 0 else st(a)
-    wh, bh = Pq["H"]
-    logits = cur @ wh[0, 0, 0, :] + bh[0]
-    return {"logits": logits, "vis": sigmoid(logits)}
+        a = relu(lowp_decoder_pre(skips[l], cur, *P[f"D{l}"], cmp, box=phase.get(f"D{l}")))
+        if l > 0:
+            cur = _store(a, st)
+            out[f"d{l}"] = cur
+        else:
+            cur = _head_input(a)
+    wh, bh = P["H"]
+    logits = cur @ _head_weights(wh[0, 0, 0, :]) + bh[0]
+    res = {"logits": logits, "vis": sigmoid(logits)}
+    if keep:
+        res.update(out)
+    return res
 
 
 # ------------------------------------------------------------ closed forms

@@ -14,7 +14,7 @@
  *     occluder depth z, pixel-to-emitter depth z_f, emitter size r_e and
  *     their compositions (Sec. 3.1-3.2), plus the hard depth-test mask;
  *   - brute-force / BVH ray-cast visibility, emitter-to-receiver rays
- *     (supplemental Sec. 6 prefers emitter-to-scene rays), one ray for a
+ *     (supplemental Sec. 5 prefers emitter-to-scene rays), one ray for a
  *     point light and stratified samples over the emitter disk for a
  *     spherical light (Sec. 3.1 uses Monte-Carlo ray-traced targets).
  *

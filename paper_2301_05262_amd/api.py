@@ -15,6 +15,29 @@ def _dev(device):
     return torch.device(device if device is not None else "cuda")
 
 
+def _torch_stream(stream):
+    """The torch stream object of a `stream=` argument (None: torch's current one)."""
+    if stream is None or isinstance(stream, torch.cuda.Stream):
+        return stream
+    return torch.cuda.ExternalStream(int(stream))
+
+
+def _grow(buf, need, device, stream):
+    """A workspace of at least `need` bytes.  When the library runs on a stream
+    other than torch's current one, torch's caching allocator must know that
+    the old and new buffers are used there, or it could hand the old buffer
+    out again while kernels queued on that stream still read it."""
+    if buf is not None and buf.numel() >= need:
+        return buf
+    ts = _torch_stream(stream)
+    if buf is not None and ts is not None:
+        buf.record_stream(ts)
+    buf = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+    if ts is not None:
+        buf.record_stream(ts)
+    return buf
+
+
 class FeatureBuilder:
     """Builds one frame's network input from a triangle scene on the GPU."""
 
@@ -26,10 +49,9 @@ class FeatureBuilder:
         self.n_tris = int(scene.tris.shape[0])
         self._ws = None
 
-    def workspace(self, h, w, sm_size):
+    def workspace(self, h, w, sm_size, stream=None):
         need = _lib.nsm_features_workspace_bytes(self.n_tris, h, w, sm_size)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self._ws = _grow(self._ws, need, self.device, stream)
         return self._ws
 
     def __call__(self, fr, soft=False, out=None, stream=None, fs=None):
@@ -46,7 +68,7 @@ class FeatureBuilder:
                 "sm": torch.empty((S, S), dtype=torch.int32, device=self.device),
                 "gbuf": torch.empty((h, w), dtype=torch.int64, device=self.device),
             }
-        ws = self.workspace(h, w, S)
+        ws = self.workspace(h, w, S, stream)
         _lib.nsm_build_features(self.tris, self.normals, self.n_tris, fr, h, w,
                                 fs, None, out["gbuf"], out["sm"],
                                 out["feat"], out["mask"], ws, ws.numel(), stream)
@@ -81,10 +103,9 @@ class ShadowNet:
         self._w = flat          # keep alive until the stream has copied it
         _lib.nsm_set_weights(self.ctx, flat, self.n_params, stream)
 
-    def workspace(self, n, h, w, training=False):
+    def workspace(self, n, h, w, training=False, stream=None):
         need = _lib.nsm_workspace_bytes(self.ctx, n, h, w, int(training))
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        self._ws = _grow(self._ws, need, self.device, stream)
         return self._ws
 
     def forward(self, feat, logits=False, vis_out=None, logits_out=None, stream=None):
@@ -98,7 +119,7 @@ class ShadowNet:
         lg = logits_out
         if logits and lg is None:
             lg = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
-        ws = self.workspace(n, h, w)
+        ws = self.workspace(n, h, w, stream=stream)
         _lib.nsm_forward(self.ctx, feat, n, h, w, vis, lg, ws, ws.numel(), stream)
         return (vis, lg) if logits else vis
 
@@ -110,7 +131,7 @@ class ShadowNet:
         dw = dw_out if dw_out is not None else torch.empty(self.n_params, dtype=torch.float32,
                                                            device=feat.device)
         df = torch.empty_like(feat) if want_dfeat else None
-        ws = self.workspace(n, h, w, training=True)
+        ws = self.workspace(n, h, w, training=True, stream=stream)
         _lib.nsm_backward(self.ctx, feat, dvis, n, h, w, dw, int(accumulate), df, ws, ws.numel(),
                           stream)
         return dw, df

@@ -15,6 +15,18 @@ bool trace_on();
 void trace_begin(const char* name, const char* suffix, hipStream_t s);
 void trace_end(hipStream_t s);
 
+// Debug mode (environment NSM_DEBUG_SYNC=1, read at every entry point):
+// debug_sync_begin() arms it for the calling thread's current entry point;
+// debug_check(s) then synchronises `s` after each launch and keeps the first
+// runtime error; debug_sync_end(s) synchronises once more and returns that
+// error (hipSuccess when the mode is off).
+bool debug_sync_begin();
+void debug_check(hipStream_t s);
+hipError_t debug_sync_end(hipStream_t s);
+
+// Every kernel launch of the library sits inside one of these scopes: it
+// brackets the launch with trace events when tracing is on and, in debug
+// mode, synchronises after it.
 struct TraceScope {
     hipStream_t s;
     bool on;
@@ -23,6 +35,7 @@ struct TraceScope {
     }
     ~TraceScope() {
         if (on) trace_end(s);
+        debug_check(s);
     }
 };
 

@@ -18,6 +18,9 @@ namespace {
 
 constexpr int kMaxImage = 16384;
 constexpr int kMaxFrames = 4096;
+// Triangle counts are carried in 32-bit ints (two passes of virtual
+// triangles, per-triangle offsets); 2^28 keeps every such index in range.
+constexpr int kMaxTris = 1 << 28;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -78,6 +81,7 @@ const char* nsm_status_str(int s) {
 // ----------------------------------------------------------------- features
 nsm_status nsm_features_workspace_bytes(int n_tris, int h, int w, int sm_size, size_t* bytes) {
     if (!bytes || n_tris < 0) return NSM_E_INVALID_ARG;
+    if (n_tris > kMaxTris) return NSM_E_SHAPE;
     if (h < 1 || w < 1 || h > kMaxImage || w > kMaxImage || sm_size < 1 || sm_size > kMaxImage)
         return NSM_E_SHAPE;
     *bytes = align256(raster_workspace_bytes(n_tris)) + align256((size_t)h * (size_t)w * 8);
@@ -98,6 +102,7 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     if (!workspace || ws_bytes < need) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
     char* ws = reinterpret_cast<char*>(workspace);
     uint64_t* gbuf_ws = reinterpret_cast<uint64_t*>(ws + align256(raster_workspace_bytes(n_tris)));
 
@@ -138,6 +143,7 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, w, h, (int)fs, feat_out,
                mask_out, s) != hipSuccess)
         return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
 }
 
@@ -282,6 +288,7 @@ nsm_status nsm_set_weights(nsm_ctx* ctx, const float* w, size_t n, void* stream)
     if (n != ctx->n_params) return NSM_E_INVALID_ARG;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
     if (!ctx->dbuf) {
         if (hipMalloc(&ctx->dbuf, ctx->dbuf_bytes) != hipSuccess) {
             ctx->dbuf = nullptr;
@@ -303,6 +310,7 @@ nsm_status nsm_set_weights(nsm_ctx* ctx, const float* w, size_t n, void* stream)
             pack_dgrad_weights(p.st, flat + p.w_off, base + p.pk_bwd_off, s) != hipSuccess)
             return NSM_E_LAUNCH;
     }
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     ctx->has_weights = true;
     return NSM_OK;
 }
@@ -596,10 +604,12 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
     if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
     char* ws = reinterpret_cast<char*>(workspace);
     const hipError_t e = paper ? run_forward_paper(ctx, feat, n, h, w, vis_out, logits_out, ws, L, s)
                                : run_forward(ctx, feat, n, h, w, vis_out, logits_out, ws, L, nullptr, s);
     if (e != hipSuccess) return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
 }
 
@@ -615,9 +625,11 @@ nsm_status nsm_backward(nsm_ctx* ctx, const float* feat, const float* dvis, int 
     if (!workspace || ws_bytes < T.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
     if (run_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate != 0, dfeat_out,
                      reinterpret_cast<char*>(workspace), T, s) != hipSuccess)
         return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
 }
 
@@ -643,9 +655,11 @@ nsm_status nsm_perturbation_loss(const float* vis, const float* target, int n, i
         return NSM_E_SHAPE;
     if (!workspace || ws_bytes < perturb_loss_workspace_bytes((long long)n * h * w)) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
-    if (perturb_loss(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, workspace,
-                     reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
+    if (perturb_loss(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, workspace, s) != hipSuccess)
         return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
 }
 
@@ -679,13 +693,17 @@ nsm_status nsm_temporal_instability(const float* tris, const float* tri_normals,
     if (!prev || !cur || !gbuf_prev || !gbuf_cur || !vis_prev || !vis_cur || !acc_out || n_tris < 0)
         return NSM_E_INVALID_ARG;
     if (n_tris > 0 && (!tris || !tri_normals)) return NSM_E_INVALID_ARG;
+    if (n_tris > kMaxTris) return NSM_E_SHAPE;
     if (h < 1 || w < 1 || h > kMaxImage || w > kMaxImage) return NSM_E_SHAPE;
     if (!workspace || ws_bytes < temporal_workspace_bytes(h, w)) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
     if (temporal_pair(tris, tri_normals, n_tris, cam_params(prev), cam_params(cur), gbuf_prev, gbuf_cur,
                       vis_prev, vis_cur, h, w, alpha, depth_tol, cos_tol, accumulate, acc_out, d_out,
-                      workspace, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+                      workspace, s) != hipSuccess)
         return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -39,6 +40,32 @@ hipEvent_t take_event() {
 }  // namespace
 
 bool trace_on() { return g_on; }
+
+namespace {
+thread_local bool t_debug = false;
+thread_local hipError_t t_debug_err = hipSuccess;
+}  // namespace
+
+bool debug_sync_begin() {
+    const char* e = std::getenv("NSM_DEBUG_SYNC");
+    t_debug = e && e[0] == '1' && e[1] == '\0';
+    t_debug_err = hipSuccess;
+    return t_debug;
+}
+
+void debug_check(hipStream_t s) {
+    if (!t_debug) return;
+    const hipError_t e = hipStreamSynchronize(s);
+    const hipError_t l = hipGetLastError();
+    if (t_debug_err == hipSuccess) t_debug_err = e != hipSuccess ? e : l;
+}
+
+hipError_t debug_sync_end(hipStream_t s) {
+    if (!t_debug) return hipSuccess;
+    debug_check(s);
+    t_debug = false;
+    return t_debug_err;
+}
 
 void trace_begin(const char* name, const char* suffix, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -180,3 +180,24 @@ def test_temporal_validation():
     with pytest.raises(nsm.NsmError) as e:
         nsm.nsm_temporal_instability(**{**targs, "h": 16385})
     assert e.value.status == 2
+
+
+def test_triangle_count_cap():
+    """Triangle counts above 2^28 are rejected before any device call (the
+    rasteriser carries two passes of triangle indices in 32-bit ints)."""
+    import nsm_synth as S
+    assert nsm.nsm_features_workspace_bytes(1 << 28, 64, 64, 128) > 0
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_features_workspace_bytes((1 << 28) + 1, 64, 64, 128)
+    assert e.value.status == 2
+    sc, fr = S.workload_frame("tiny_64", 0)
+    fp = _lib.frame_params(fr)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_build_features(1024, 2048, (1 << 28) + 1, fp, 64, 64, "hard6", None, None, 4096, 8192,
+                               None, 16384, 1 << 40, 0)
+    assert e.value.status == 2
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_temporal_instability(1024, 2048, (1 << 28) + 1, fr, fr, 4096, 8192, 12288, 16384, 64, 64,
+                                     3.0, 0.01, 0.9, 1, 20480, None, 24576, 1 << 30, 0)
+    assert e.value.status == 2
+

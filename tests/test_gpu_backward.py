@@ -135,6 +135,55 @@ def _clear_windows(desc, flat, feat, axis, length=8, count=8):
     return picked, act
 
 
+def _near_ties(desc, flat, act):
+    """[(level, mask [N, H_l, W_l], reach)] of the float64 forward's decisions
+    within float32 rounding of a tie (ReLU pre-activations and max-pool gaps,
+    bound EPS_TIE * sum |w| |x| + |b|)."""
+    P = onet.split_params(desc.c_in, desc.widths, flat)
+    L = len(desc.widths)
+    inputs = {"E0": act["x"], "B": act[f"p_E{L - 2}"]}
+    for l in range(1, L - 1):
+        inputs[f"E{l}"] = act[f"p_E{l - 1}"]
+    for l in range(L - 1):
+        inputs[f"D{l}"] = np.concatenate([act[f"a_E{l}"], act[f"up_D{l}"]], -1)
+    level = {"B": L - 1, **{f"E{l}": l for l in range(L - 1)}, **{f"D{l}": l for l in range(L - 1)}}
+    out = []
+    for name, x in inputs.items():
+        w, b = P[name]
+        A = onet.conv3x3(np.abs(x), np.abs(w), np.abs(b))
+        out.append((level[name], (np.abs(act["z_" + name]) <= EPS_TIE * A).any(axis=3), REACH[name]))
+        if name.startswith("E"):
+            n, h, w_, c = A.shape
+            win = lambda t: t.reshape(n, h // 2, 2, w_ // 2, 2, c).transpose(0, 1, 3, 2, 4, 5).reshape(
+                n, h // 2, w_ // 2, 4, c)
+            a, sa = win(act["a_" + name]), win(A)
+            top = a.max(axis=3, keepdims=True)
+            close = ((top - a <= EPS_TIE * sa) & (a < top) & (top > 0)).any(axis=3).any(axis=3)
+            out.append((level[name] + 1, close, REACH["pool" + name[1:]]))
+    return out
+
+
+def _clear_mask(desc, flat, feat):
+    """Level-0 pixels that no near-tie decision of the float64 forward can
+    reach (2-D form of _clear_windows): a visibility gradient confined to
+    them meets only decisions that float32 takes as float64 does."""
+    act = onet.forward(desc.c_in, desc.widths, flat, feat)
+    n, H, W = feat.shape[:3]
+    blocked = np.zeros((n, H + 1, W + 1), np.int64)
+    for lev, mask, reach in _near_ties(desc, flat, act):
+        f, i, j = np.nonzero(mask)
+        y0 = np.clip(i * (1 << lev) - reach, 0, H)
+        y1 = np.clip((i + 1) * (1 << lev) + reach, 0, H)
+        x0 = np.clip(j * (1 << lev) - reach, 0, W)
+        x1 = np.clip((j + 1) * (1 << lev) + reach, 0, W)
+        np.add.at(blocked, (f, y0, x0), 1)
+        np.add.at(blocked, (f, y1, x0), -1)
+        np.add.at(blocked, (f, y0, x1), -1)
+        np.add.at(blocked, (f, y1, x1), 1)
+    cover = blocked.cumsum(axis=1).cumsum(axis=2)[:, :H, :W]
+    return cover == 0
+
+
 @pytest.mark.parametrize("shape", [(1, 20, 16384), (1, 16384, 20)])
 def test_backward_maximum_extent(shape):
     """The longest image side the library takes (16384), 20 pixels across.
@@ -167,66 +216,121 @@ def test_backward_maximum_extent(shape):
     assert np.all(df[ref_f == 0] == 0)
 
 
+def _soft_window_case(desc, seed, frames, width, height, sm_size):
+    sc, frs = S.make_train_window(0, seed, width=width, height=height, sm_size=sm_size)
+    feat = np.stack([oracle.build_features(sc, fr, soft=True)["feat"] for fr in frs[:frames]])
+    return feat
+
+
+def _check_soft_backward(desc, flat, feat, seed, tag, min_clear, dense_rel):
+    """Gradient on the oracle's clear pixels only: dW per stage and dfeat
+    element-wise at the usual tolerance, and dfeat exactly zero wherever the
+    oracle's is.  Dense visibility gradient: dW per stage within
+    `dense_rel`.  A dense gradient meets every ReLU and max-pool decision
+    that float32 rounding can flip; each flip moves a gradient contribution
+    to another pixel, so over millions of pixels dW moves by more than the
+    float32 accumulation error (on the 4 x 512^2 window about 1e-3 of its
+    largest entry), while the clear-pixel gradient, which meets no such
+    decision, agrees to 1e-4."""
+    dvis = _rand(feat.shape[:3], seed)
+    ref_w, _ = onet.backward(desc.c_in, desc.widths, flat, feat, dvis)
+    m = _net(desc, flat)
+    dw, _ = _gpu_grads(m, feat, dvis, want_dfeat=False)
+    per = _stage_errors(desc, dw, ref_w)
+    print(f"[{tag}] dense dvis: dW per-stage rel err {per}", flush=True)
+    assert max(per.values()) <= dense_rel
+    clear = _clear_mask(desc, flat, feat)
+    frac = float(clear.mean())
+    dvc = (dvis * clear).astype(np.float32)
+    ref_w, ref_f = onet.backward(desc.c_in, desc.widths, flat, feat, dvc)
+    dw, df = _gpu_grads(m, feat, dvc)
+    per = _stage_errors(desc, dw, ref_w)
+    e_f = np.abs(df - ref_f).max() / np.abs(ref_f).max()
+    print(f"[{tag}] dvis on the {frac:.1%} clear pixels: dW per-stage rel err {per}  dfeat {e_f:.3e}",
+          flush=True)
+    assert frac >= min_clear
+    assert max(per.values()) <= REL and e_f <= REL
+    assert np.all(df[ref_f == 0] == 0)
+
+
 def test_backward_on_soft_shadow_features():
     """Rendered soft-shadow features are smooth, so thousands of 2x2 pooling
     windows hold two values that differ by less than float32 accumulation
     error (1e-7..1e-6): which one is the maximum, and so where the window's
     gradient goes, is not fixed at float32.  (A float32 PyTorch CPU forward
     on this input picks a different maximum than float64 in 37 windows and
-    moves 6% of the dfeat elements.)  What the routing cannot change is
-    compared tightly: dW (a sum over all pixels) per stage, and the sum of
-    dfeat over the image per frame and channel (a routed gradient keeps its
-    value, only its pixel changes).  The rest is checked for validity: most
-    elements must still agree and the norm must be kept.  Element-wise parity
-    of dfeat is the random-feature test above."""
-    sc, frames = S.make_train_window(0, 3, width=128, height=96, sm_size=512)
-    feat = np.stack([oracle.build_features(sc, fr, soft=True)["feat"] for fr in frames[:2]])
-    flat = S.he_weights(S.U3_SOFT, 2, bias_scale=0.1)
-    dvis = _rand(feat.shape[:3], 24)
-    ref_w, ref_f = onet.backward(8, S.U3_SOFT.widths, flat, feat, dvis)
-    dw, df = _gpu_grads(_net(S.U3_SOFT, flat), feat, dvis)
-    per = _stage_errors(S.U3_SOFT, dw, ref_w)
-    sums = np.abs(df.sum(axis=(1, 2)) - ref_f.sum(axis=(1, 2))) / np.abs(ref_f).sum(axis=(1, 2))
-    agree = (np.abs(df - ref_f) <= REL * np.abs(ref_f).max()).mean()
-    norm = abs(np.linalg.norm(df) - np.linalg.norm(ref_f)) / np.linalg.norm(ref_f)
-    print(f"[soft features] dW per-stage rel err {per}  dfeat channel sums {sums.max():.2e}  "
-          f"agree {agree:.2%}  norm {norm:.2e}", flush=True)
-    assert max(per.values()) <= REL
-    assert sums.max() <= 1e-4
-    assert agree >= 0.85 and norm <= 1e-2
+    moves 6% of the dfeat elements.)  So dfeat is compared element-wise for a
+    visibility gradient on the pixels that no such decision reaches (chosen
+    on the float64 oracle alone); dW also with a dense gradient."""
+    feat = _soft_window_case(S.U3_SOFT, 3, 2, 128, 96, 512)
+    _check_soft_backward(S.U3_SOFT, S.he_weights(S.U3_SOFT, 2, bias_scale=0.1), feat, 24, "soft 2x96x128", 0.01, REL)
+
+
+def test_backward_training_window_512():
+    """One full training window of the soft-shadow training step (4 consecutive
+    512 x 512 frames, SOFT8 rendered features, the U-Net the step trains) --
+    at this scale every wgrad block reduces ~100 tiles.  Gradient on the
+    clear pixels (about 14% of them, spread over all four frames): dW and
+    dfeat element-wise; dense gradient: dW per stage within 5e-3 (decision
+    flips near ties, see _check_soft_backward)."""
+    feat = _soft_window_case(S.U3_SOFT, 0, 4, 512, 512, 1024)
+    _check_soft_backward(S.U3_SOFT, S.he_weights(S.U3_SOFT, 0, bias_scale=0.1), feat, 29, "window 4x512x512",
+                         0.1, 5e-3)
 
 
 def test_finite_differences_on_crop():
-    """float32 central differences of the GPU forward vs the GPU gradient, 16x16 crop."""
+    """Central differences of the GPU forward against the GPU gradient on a
+    16x16 crop, relative error <= 5% with no absolute floor.
+
+    The perturbed weights are formed in float64 and rounded to the float32
+    the library takes; the difference quotient divides by the step actually
+    taken.  For each weight the step is the largest of 2e-2 .. 1e-3 at which
+    the float64 oracle's own central difference (same rounded weights) is
+    within 1% of the float64 adjoint, i.e. no ReLU kink or curvature spoils
+    the quotient at that step; the float32 noise of J (about 1e-5 over 256
+    pixels, so 5e-3 in the quotient at the smallest step) stays below 1% of
+    the gradients tested (the largest ones, about 2 and up)."""
     desc = S.U3
     flat = S.he_weights(desc, 25, bias_scale=0.1)
     feat = _rand((1, 16, 16, 6), 26)
     dvis = _rand((1, 16, 16), 27)
     m = _net(desc, flat)
     dw, df = _gpu_grads(m, feat, dvis)
+    ref_w, _ = onet.backward(desc.c_in, desc.widths, flat, feat, dvis)
     f = torch.from_numpy(feat).cuda()
     d = torch.from_numpy(dvis).cuda().double()
 
-    def J(p):
-        m.set_weights(torch.from_numpy(p.astype(np.float32)))
+    def J(p32):
+        m.set_weights(torch.from_numpy(p32))
         v = m.forward(f).double()
         return float((v * d).sum())
 
-    # weights with sizeable gradients.  Step 1e-3: at 1e-2 the second-order terms
-    # and ReLU kinks crossed by the step already move float64 central differences of
-    # the exact network 5-10% off its gradient; at 1e-3 float32 roundoff of J
-    # (~1e-5 over 256 pixels) gives ~5e-3 absolute noise in the difference quotient
+    def J64(p32):
+        return float((onet.forward(desc.c_in, desc.widths, p32, feat, keep=False)["vis"] * dvis).sum())
+
     order = np.argsort(-np.abs(dw))
     rng = S.SplitMix64(28)
-    pick = sorted({int(order[int(rng.uniform(0, 400))]) for _ in range(25)})
-    assert abs(dw[pick]).min() > 5e-2
+    pick = sorted({int(order[int(rng.uniform(0, 400))]) for _ in range(30)})
+    assert abs(dw[pick]).min() > 1.0
+    tested = 0
     for i in pick:
-        hstep = 1e-3
-        p, q = flat.astype(np.float64).copy(), flat.astype(np.float64).copy()
-        p[i] += hstep
-        q[i] -= hstep
-        fd = (J(p) - J(q)) / (2 * hstep)
-        assert abs(fd - dw[i]) <= 3e-2 * abs(dw[i]) + 1e-2, (i, fd, dw[i])
+        for hstep in (2e-2, 1e-2, 5e-3, 2e-3, 1e-3):
+            p, q = flat.astype(np.float64).copy(), flat.astype(np.float64).copy()
+            p[i] += hstep
+            q[i] -= hstep
+            p32, q32 = p.astype(np.float32), q.astype(np.float32)
+            step = (float(p32[i]) - float(q32[i])) / 2.0
+            fd64 = (J64(p32) - J64(q32)) / (2 * step)
+            if abs(fd64 - ref_w[i]) <= 1e-2 * abs(ref_w[i]):
+                break
+        else:
+            continue
+        fd = (J(p32) - J(q32)) / (2 * step)
+        print(f"[fd] w[{i}] step {step:.3e}: fd {fd:.6f} gpu grad {dw[i]:.6f} "
+              f"({abs(fd - dw[i]) / abs(dw[i]):.2e})", flush=True)
+        assert abs(fd - dw[i]) <= 5e-2 * abs(dw[i]), (i, fd, dw[i])
+        tested += 1
+    assert tested >= 20, tested
 
 
 def test_autograd_function_and_training_step():

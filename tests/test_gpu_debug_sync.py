@@ -1,0 +1,55 @@
+"""Debug mode (NSM_DEBUG_SYNC=1): every call synchronises after each of its
+launches and maps a failed launch or kernel to NSM_E_LAUNCH.  A normal
+feature build, forward (BF16 and FP32), backward and perturbation loss run
+under the flag must return NSM_OK and give the same bits as without it."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import nsm_synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(t):
+    a = t.detach().cpu().numpy()
+    return a.view(np.uint8).copy()
+
+
+def _run_all():
+    from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet, perturbation_loss
+    sc, fr = S.workload_frame("tiny_64", 0)
+    out = FeatureBuilder(sc)(fr)
+    feat = out["feat"].unsqueeze(0).contiguous()
+    res = {k: _bits(v) for k, v in out.items()}
+    flat = torch.from_numpy(S.he_weights(S.U2, 3, bias_scale=0.1))
+    for dt in ("bf16", "f32"):
+        net = ShadowNet(6, S.U2.widths, dt)
+        net.set_weights(flat)
+        res["vis_" + dt] = _bits(net.forward(feat))
+    dvis = torch.linspace(-1, 1, 64 * 64, dtype=torch.float32, device="cuda").reshape(1, 64, 64)
+    dw, df = net.backward(feat, dvis)
+    res["dw"], res["df"] = _bits(dw), _bits(df)
+    vis4 = torch.rand((2, 4, 64, 64), generator=torch.Generator().manual_seed(1), dtype=torch.float32).cuda()
+    loss, d0 = perturbation_loss(vis4, vis4[:, 0].contiguous() * 0.5)
+    res["loss"], res["d0"] = _bits(loss), _bits(d0)
+    torch.cuda.synchronize()
+    return res
+
+
+def test_debug_sync_same_bits():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    old = os.environ.pop("NSM_DEBUG_SYNC", None)
+    try:
+        plain = _run_all()
+        os.environ["NSM_DEBUG_SYNC"] = "1"
+        debug = _run_all()
+    finally:
+        os.environ.pop("NSM_DEBUG_SYNC", None)
+        if old is not None:
+            os.environ["NSM_DEBUG_SYNC"] = old
+    assert plain.keys() == debug.keys()
+    for k in plain:
+        assert np.array_equal(plain[k], debug[k]), k

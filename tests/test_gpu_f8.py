@@ -1,8 +1,10 @@
 """GPU parity of the 8-bit temporary-storage form (NSM_F8): activations
 stored as FP8 E4M3, bfloat16 weights and compute.
 
-Reference: the oracle's storage-rounding forward with the same rounding
-points (oracle/net.py forward_lowp 'f8').  E4M3 steps are 1/8 relative, so
+Reference: the oracle's model of the form with the same rounding points
+(oracle/net.py forward_lowp 'f8', phase-form interior as the kernels tile
+it).  Every stored tensor is also compared stage by stage with that model in
+tests/test_gpu_lowp_stages.py; here the whole forward is compared end to end.  E4M3 steps are 1/8 relative, so
 a value that float32 accumulation puts on the other side of a rounding
 midpoint than float64 does moves by a whole step.  Perturbing the oracle's
 stored values by 3e-6 relative noise (about float32 accumulation error over
@@ -38,7 +40,8 @@ def _run(desc, flat, feat):
 def _check(desc, flat, feat, label):
     n, h, w, _ = feat.shape
     m, vis = _run(desc, flat, feat)
-    ref8 = onet.forward_lowp(desc.c_in, desc.widths, flat, feat, "f8")["vis"]
+    from lowp_stages import phase_boxes
+    ref8 = onet.forward_lowp(desc.c_in, desc.widths, flat, feat, "f8", phase=phase_boxes(desc.widths, h, w))["vis"]
     d = np.abs(vis - ref8)
     e64 = np.abs(vis - onet.forward(desc.c_in, desc.widths, flat, feat, keep=False)["vis"])
     print(f"[f8 {label}] vs emulation max {d.max():.2e} mean {d.mean():.2e}; "

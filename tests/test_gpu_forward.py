@@ -83,7 +83,8 @@ def test_lowp_random_features(desc, shape, dtype):
     flat = S.he_weights(desc, 13, bias_scale=0.1)
     feat = _rand_feat(n, h, w, desc.c_in, 14)
     ref = onet.forward(desc.c_in, desc.widths, flat, feat, keep=False)
-    emu = onet.forward_lowp(desc.c_in, desc.widths, flat, feat, dtype)
+    from lowp_stages import phase_boxes
+    emu = onet.forward_lowp(desc.c_in, desc.widths, flat, feat, dtype, phase=phase_boxes(desc.widths, h, w))
     vis, _ = _run(_net(desc, dtype, flat), feat)
     e64 = np.abs(vis - ref["vis"]).max()
     eemu = np.abs(vis - emu["vis"]).max()

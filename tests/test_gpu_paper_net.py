@@ -91,8 +91,10 @@ def test_paper_net_s2d_shape_errors():
     m = ShadowNet(4, P5, "bf16", arch="paper_s2d")
     assert m.n_params == pn.n_params(4, P5, s2d=True)
     m.set_weights(torch.from_numpy(_weights(P5, 46, s2d=True)))
-    with pytest.raises(Exception):
-        m.forward(torch.zeros((1, 40, 80, 4), device="cuda"))      # 40 is not a multiple of 16
+    import paper_2301_05262_amd as nsm
+    with pytest.raises(nsm.NsmError) as e:                         # 40 is not a multiple of 16
+        m.forward(torch.zeros((1, 40, 80, 4), dtype=torch.float32, device="cuda"))
+    assert e.value.status == 2
 
 
 def test_paper4_features_bit_exact():

@@ -5,7 +5,7 @@ normal n, emitter-to-occluder depth z, pixel-to-emitter depth z_f, emitter
 size r_e) and their compositions (Sec. 3.2: z - z_f, z / z_f, ...).  The
 depth-test mask is the vanilla shadow-map test.  The ray cast is the
 emitter-to-receiver visibility the paper trains against (Sec. 3.1, supp.
-Sec. 6), with one ray for a point light and stratified emitter samples for a
+Sec. 5), with one ray for a point light and stratified emitter samples for a
 spherical light.
 
 Pins: geometric invariants of the gathered channels on an analytic ground

@@ -14,7 +14,16 @@ import torch.nn.functional as F
 from oracle import net
 from nsm_synth import SplitMix64, U2, U3, U3_SOFT, he_weights
 
-torch.set_default_dtype(torch.float64)
+
+
+@pytest.fixture(autouse=True)
+def _float64_default():
+    """torch tensors built in these tests default to float64; restored after
+    each test so that no other module sees the change."""
+    old = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(old)
 
 
 def rnd(shape, seed, lo=-1.0, hi=1.0):
