@@ -276,6 +276,21 @@ nsm_status nsm_perturbation_loss(const float *vis, const float *target, int n, i
                                  float alpha, double *loss_out, float *dvis0_out, void *workspace,
                                  size_t ws_bytes, void *stream);
 
+/* nsm_perturbation_loss_noalloc -- nsm_perturbation_loss for callers that
+ * cannot allocate device memory or pass a workspace (code under hipGraph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors, minus the workspace: the
+ * per-block partial sums live in a 2 MiB array that the library holds on
+ * each device it runs on until the process ends, so n * h * w is at most
+ * 67,108,864 pixels (NSM_E_SHAPE above).  It makes no allocation of any kind;
+ * the first call on a device looks up that device's copy of the array
+ * (NSM_E_DEVICE if that fails).  The kernels and the reduction order are
+ * those of nsm_perturbation_loss, so both give identical bits.  Every call
+ * on one device shares the array: calls that may overlap on one device (two
+ * streams, two threads) race and must be ordered by the caller. */
+nsm_status nsm_perturbation_loss_noalloc(const float *vis, const float *target, int n, int p, int h,
+                                         int w, float alpha, double *loss_out, float *dvis0_out,
+                                         void *stream);
 
 /* nsm_temporal_instability -- one frame pair of the temporal-instability
  * metric of paper Sec. 3.4, Eq. 3:

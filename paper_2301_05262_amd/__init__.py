@@ -26,6 +26,7 @@ from ._lib import (  # noqa: F401
     nsm_trace_read,
     nsm_perturbation_loss_workspace_bytes,
     nsm_perturbation_loss,
+    nsm_perturbation_loss_noalloc,
     nsm_temporal_workspace_bytes,
     nsm_temporal_instability,
 )

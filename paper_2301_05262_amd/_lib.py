@@ -23,7 +23,8 @@ EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
     "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
     "nsm_forward", "nsm_backward", "nsm_trace_enable", "nsm_trace_read",
-    "nsm_perturbation_loss_workspace_bytes", "nsm_perturbation_loss", "nsm_temporal_workspace_bytes",
+    "nsm_perturbation_loss_workspace_bytes", "nsm_perturbation_loss", "nsm_perturbation_loss_noalloc",
+    "nsm_temporal_workspace_bytes",
     "nsm_temporal_instability",
 ]
 
@@ -81,6 +82,7 @@ def load():
         "nsm_trace_enable": ([i32], i32),
         "nsm_perturbation_loss_workspace_bytes": ([i32, i32, i32, i32, psz], i32),
         "nsm_perturbation_loss": ([vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp, sz, vp], i32),
+        "nsm_perturbation_loss_noalloc": ([vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp], i32),
         "nsm_temporal_workspace_bytes": ([i32, i32, psz], i32),
         "nsm_temporal_instability": ([vp, vp, i32, ctypes.POINTER(FrameParams), ctypes.POINTER(FrameParams),
                                       vp, vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float,
@@ -240,6 +242,12 @@ def nsm_perturbation_loss(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, w
     _check(load().nsm_perturbation_loss(_ptr(vis), _ptr(target), n, p, h, w, float(alpha), _ptr(loss_out),
                                         _ptr(dvis0_out), _ptr(workspace), ws_bytes, _stream(stream)),
            "nsm_perturbation_loss")
+
+
+def nsm_perturbation_loss_noalloc(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, stream=None):
+    _check(load().nsm_perturbation_loss_noalloc(_ptr(vis), _ptr(target), n, p, h, w, float(alpha),
+                                                _ptr(loss_out), _ptr(dvis0_out), _stream(stream)),
+           "nsm_perturbation_loss_noalloc")
 
 
 def nsm_temporal_workspace_bytes(h, w):

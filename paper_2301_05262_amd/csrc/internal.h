@@ -92,6 +92,13 @@ struct CamParams {
     float tanx, tany;
 };
 size_t perturb_loss_workspace_bytes(long long npx);
+// Partials of the allocation-free entry point: one float64 per 256 pixels,
+// so at most kStaticLossPartials * 256 pixels per call (2 MiB of scratch).
+constexpr long long kStaticLossPartials = 1 << 18;
+constexpr long long kStaticLossMaxPixels = kStaticLossPartials * 256;
+// This device's address of the library-held partials array (looked up once
+// per device, with that device current).
+hipError_t static_loss_partials(double** out);
 hipError_t perturb_loss(const float* vis, const float* target, int n, int p, int h, int w, float alpha,
                         double* loss, float* dvis0, void* ws, hipStream_t s);
 size_t temporal_workspace_bytes(int h, int w);

@@ -663,6 +663,24 @@ nsm_status nsm_perturbation_loss(const float* vis, const float* target, int n, i
     return NSM_OK;
 }
 
+nsm_status nsm_perturbation_loss_noalloc(const float* vis, const float* target, int n, int p, int h, int w,
+                                         float alpha, double* loss_out, float* dvis0_out, void* stream) {
+    if (!vis || !target || !loss_out || !dvis0_out) return NSM_E_INVALID_ARG;
+    if (n < 1 || n > kMaxFrames || p < 0 || p > kMaxPerturb || h < 1 || w < 1 || h > kMaxImage ||
+        w > kMaxImage)
+        return NSM_E_SHAPE;
+    if ((long long)n * h * w > kStaticLossMaxPixels) return NSM_E_SHAPE;
+    if (!device_ok()) return NSM_E_DEVICE;
+    double* partials = nullptr;
+    if (static_loss_partials(&partials) != hipSuccess) return NSM_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    debug_sync_begin();
+    if (perturb_loss(vis, target, n, p, h, w, alpha, loss_out, dvis0_out, partials, s) != hipSuccess)
+        return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
+    return NSM_OK;
+}
+
 nsm_status nsm_temporal_workspace_bytes(int h, int w, size_t* bytes) {
     if (!bytes) return NSM_E_INVALID_ARG;
     if (h < 1 || w < 1 || h > kMaxImage || w > kMaxImage) return NSM_E_SHAPE;

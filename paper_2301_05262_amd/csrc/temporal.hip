@@ -23,6 +23,8 @@
 // decisions that depend on them are exact).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -195,6 +197,35 @@ __global__ void __launch_bounds__(kThreadsT)
 }
 
 }  // namespace
+
+// Scratch of the allocation-free perturbation-loss entry point: the per-block
+// float64 partial sums (one per 256 pixels), held by each device the library
+// runs on until the process ends.  In host code `scratch` names a host-side
+// stand-in; kernels get the device address from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kStaticLossPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_loss_partials(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        // the current device's copy of the array (each device holds its own)
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t perturb_loss_workspace_bytes(long long npx) {
     const long long nblk = (npx + kThreadsT - 1) / kThreadsT;

@@ -201,3 +201,18 @@ def test_triangle_count_cap():
                                      3.0, 0.01, 0.9, 1, 20480, None, 24576, 1 << 30, 0)
     assert e.value.status == 2
 
+
+def test_noalloc_loss_validation():
+    """The allocation-free perturbation loss checks its arguments like the
+    workspace form and rejects more than 2^26 pixels (its scratch limit)
+    before any device call."""
+    args = dict(vis=1024, target=2048, n=2, p=3, h=64, w=96, alpha=0.9, loss_out=4096, dvis0_out=8192,
+                stream=0)
+    with pytest.raises(nsm.NsmError) as e:
+        nsm.nsm_perturbation_loss_noalloc(**{**args, "vis": None})
+    assert e.value.status == 1
+    for bad in (dict(n=0), dict(p=17), dict(h=16385), dict(n=4096, h=128, w=129),
+                dict(n=1, h=16384, w=4097)):
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_perturbation_loss_noalloc(**{**args, **bad})
+        assert e.value.status == 2, bad
