@@ -37,7 +37,8 @@ sys.path.insert(0, ROOT)
 METRIC = "ms/frame 1080p shadow-net inference, BF16 vs FP32, at stated visibility error"
 HBM_PEAK = 8.0e12                         # B/s
 MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15,
-             "f8": 2.5e15}   # dense FLOP/s; the 8-bit storage form computes on bf16 MFMA
+             "f8": 2.5e15,    # dense FLOP/s; the 8-bit storage form computes on bf16 MFMA
+             "f8mfma": 5.0e15}
 WORKLOAD = "hard_1080p"
 CALIB_COPY_BYTES = 256 << 20
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "hbm_traffic_1080p_bf16.md")
@@ -61,12 +62,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", default="frame", choices=["frame", "none"])
-    ap.add_argument("--forms", default="bf16,f32,f16,f8")
+    ap.add_argument("--forms", default="bf16,f32,f16,f8,f8mfma")
     ap.add_argument("--batched", type=int, default=1, help="also time the 16-frame graph batch")
     ap.add_argument("--paper-net", type=int, default=1, help="also time the paper's 5-level net")
     ap.add_argument("--training", type=int, default=1, help="also time the 32-frame FP32 training step")
     ap.add_argument("--temporal", type=int, default=1,
                     help="also time the perturbation-loss training step and the temporal metric")
+    ap.add_argument("--f4", type=int, default=1,
+                    help="also run the penumbra-width level analysis and Eq. 1 on the training frames")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="end with one plain 256 MiB device copy (the scale for HBM byte counters)")
     return ap.parse_args()
@@ -75,9 +78,9 @@ def parse():
 def stage_costs(widths, c_in, h, w, dtype):
     """Algorithmic FLOPs and HBM bytes per frame of each conv stage (fused:
     every tensor written once and read once per consumer; weights included).
-    Activations take 4, 2 or (8-bit storage) 1 byte; weights 4 or 2."""
-    es = {"f32": 4, "f8": 1}.get(dtype, 2)
-    ws = 4 if dtype == "f32" else 2
+    Activations take 4, 2 or (8-bit forms) 1 byte; weights 4, 2 or (FP8 compute) 1."""
+    es = {"f32": 4, "f8": 1, "f8mfma": 1}.get(dtype, 2)
+    ws = {"f32": 4, "f8mfma": 1}.get(dtype, 2)
     w0, w1, w2 = widths
     L1, L2 = (h // 2) * (w // 2), (h // 4) * (w // 4)
     L0 = h * w
@@ -106,7 +109,7 @@ def stage_costs(widths, c_in, h, w, dtype):
 def _base(name):
     """Traced kernel name without its trailing storage-type suffix."""
     head, _, last = name.rpartition(" ")
-    return head if last in ("bf16", "f16", "f32", "f8") else name
+    return head if last in ("bf16", "f16", "f32", "f8", "f8mfma") else name
 
 
 def raster_costs(n_tris, h, w, sm):
@@ -150,7 +153,7 @@ def class_rooflines(results, costs_of, forms):
             out["raster+gather (hbm)"] = frac(form, feat, "bytes", HBM_PEAK)
         if form == "f32":
             out["fp32 convs (fp32 mfma)"] = frac(form, convs, "flops", MFMA_PEAK["f32"])
-        elif form in ("bf16", "f16", "f8"):
+        elif form in ("bf16", "f16", "f8", "f8mfma"):
             out[f"{form} thin convs E0,E1,B,D0 (hbm)"] = frac(form, thin, "bytes", HBM_PEAK)
             out[f"{form} D1 (mfma)"] = frac(form, d1, "flops", MFMA_PEAK[form])
     return out
@@ -159,55 +162,60 @@ def class_rooflines(results, costs_of, forms):
 def batched_section(S, torch, seed, reps):
     """16 mixed-size frames (1280x720 / 1920x1080 / 2560x1440, 20k-100k triangles,
     hard and soft lights): features + SOFT8 BF16 network per size group, one
-    captured graph per batch, against one-by-one FP32 launches."""
+    graph per group with the launch variants autotuned for its shape, replayed
+    in order.  Per-frame latency is the completion time of the frame's group
+    since the batch started.  Beside it: the same graphs with the default
+    variants, and one-by-one launches (features + network per frame) in BF16
+    and in FP32."""
     from paper_2301_05262_amd.api import ShadowNet
     from paper_2301_05262_amd.batch import BatchedPipeline
     frames = S.make_batched_frames(seed, 16)
     flat = torch.from_numpy(S.he_weights(S.U3_SOFT, seed))
-    pipe = BatchedPipeline(frames, 8, S.U3_SOFT.widths, flat, "bf16")
-    pipe.capture()
+    out = {"workload": "batched_mixed", "frames": len(frames),
+           "megapixels": sum(fr.width * fr.height for _, fr in frames) / 1e6,
+           "tris": [sc.n_tris for sc, _ in frames]}
+    for label, tune in (("graph_bf16_default", False), ("graph_bf16_tuned", True)):
+        pipe = BatchedPipeline(frames, 8, S.U3_SOFT.widths, flat, "bf16")
+        pipe.capture(tune=tune)
+        for _ in range(3):
+            pipe.replay()
+        batch_ms, frame_ms = [], []
+        for _ in range(reps):
+            b, done = pipe.replay_timed()
+            batch_ms.append(b)
+            frame_ms += done
+        bm, fm = np.array(batch_ms), np.array(frame_ms)
+        out[label] = {"ms_per_batch_p50": float(np.median(bm)), "ms_per_batch_p99": float(np.quantile(bm, 0.99)),
+                      "frames_per_s": len(frames) / (float(bm.mean()) / 1e3),
+                      "frame_latency_ms_p50": float(np.median(fm)), "frame_latency_ms_p99": float(np.quantile(fm, 0.99)),
+                      "variants_per_group": {f"{g['hw'][1]}x{g['hw'][0]}": g["variants"] for g in pipe.groups}}
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    for _ in range(3):
-        pipe.replay()
-    batch_ms = []
-    for _ in range(reps):
-        a, b = ev(), ev()
-        a.record()
-        pipe.replay()
-        b.record()
-        b.synchronize()
-        batch_ms.append(a.elapsed_time(b))
-    net32 = ShadowNet(8, S.U3_SOFT.widths, "f32")
-    net32.set_weights(flat)
-    slots = []
-    for g in pipe.groups:
-        for k, i in enumerate(g["idx"]):
-            slots.append((i, g["bufs"][k], g["feat"][k].unsqueeze(0), torch.empty_like(g["vis"][k:k + 1])))
-    for i, buf, f, v in slots:                       # warm-up (workspaces)
-        pipe.builders[i](frames[i][1], soft=True, out=buf)
-        net32.forward(f, vis_out=v)
-    torch.cuda.synchronize()
-    frame_ms = []
-    for _ in range(max(1, reps // 4)):
-        for i, buf, f, v in slots:
-            a, b = ev(), ev()
-            a.record()
+    for dt in ("bf16", "f32"):
+        net = ShadowNet(8, S.U3_SOFT.widths, dt)
+        net.set_weights(flat)
+        slots = []
+        for g in pipe.groups:
+            for k, i in enumerate(g["idx"]):
+                slots.append((i, g["bufs"][k], g["feat"][k].unsqueeze(0), torch.empty_like(g["vis"][k:k + 1])))
+        for i, buf, f, v in slots:                       # warm-up (workspaces)
             pipe.builders[i](frames[i][1], soft=True, out=buf)
-            net32.forward(f, vis_out=v)
-            b.record()
-            b.synchronize()
-            frame_ms.append(a.elapsed_time(b))
-    mpx = sum(fr.width * fr.height for _, fr in frames) / 1e6
-    bm, fm = np.array(batch_ms), np.array(frame_ms)
-    return {
-        "workload": "batched_mixed", "frames": len(frames), "megapixels": mpx,
-        "tris": [sc.n_tris for sc, _ in frames],
-        "graph_bf16": {"ms_per_batch_p50": float(np.median(bm)), "ms_per_batch_p99": float(np.quantile(bm, 0.99)),
-                       "frames_per_s": len(frames) / (float(bm.mean()) / 1e3),
-                       "note": "all frames of a batch complete together: per-frame latency = batch time"},
-        "one_by_one_f32": {"ms_per_frame_p50": float(np.median(fm)), "ms_per_frame_p99": float(np.quantile(fm, 0.99)),
-                           "frames_per_s": 1e3 / float(fm.mean())},
-    }
+            net.forward(f, vis_out=v)
+        torch.cuda.synchronize()
+        frame_ms = []
+        for _ in range(max(1, reps // 4)):
+            for i, buf, f, v in slots:
+                a, b = ev(), ev()
+                a.record()
+                pipe.builders[i](frames[i][1], soft=True, out=buf)
+                net.forward(f, vis_out=v)
+                b.record()
+                b.synchronize()
+                frame_ms.append(a.elapsed_time(b))
+        fm = np.array(frame_ms)
+        out[f"one_by_one_{dt}"] = {"ms_per_frame_p50": float(np.median(fm)),
+                                   "ms_per_frame_p99": float(np.quantile(fm, 0.99)),
+                                   "frames_per_s": 1e3 / float(fm.mean())}
+    return out
 
 
 def training_section(S, torch, seed, steps):
@@ -330,6 +338,39 @@ def temporal_section(S, torch, seed, steps):
                               "dtype": "f32"},
             "metric_1080p": {"ms_per_pair": pair_ms,
                              "kernels_us": {k: 1e3 * float(np.mean(v)) for k, v in per.items()}}}
+
+
+def f4_section(S, torch, seed):
+    """Design-time analysis on the soft-shadow training set (8 windows x 4
+    frames of 512^2, spherical lights r_e in [0.02, 0.2]): per-pixel
+    penumbra widths from the rendered G-buffer and shadow map (Sec. 3.6,
+    supplemental Sec. 4), their P95 and the level count the receptive-field
+    rule picks, against the 3 levels the U-Net has; and Eq. 1's relative
+    channel sensitivity of the (random-weight) SOFT8 U-Net on rendered
+    features of one window."""
+    from paper_2301_05262_amd.analysis import level_report, penumbra_widths, receptive_field, sensitivity
+    from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet
+    t0 = time.perf_counter()
+    maps, feats0 = [], []
+    for k in range(8):
+        sc, frames = S.make_train_window(seed, k)
+        fb = FeatureBuilder(sc)
+        tris, nrm = torch.from_numpy(sc.tris).cuda(), torch.from_numpy(sc.normals).cuda()
+        for fr in frames:
+            out = fb(fr, soft=True)
+            maps.append(penumbra_widths(out["gbuf"], out["sm"], tris, nrm, fr)[0].cpu().numpy())
+            if k == 0:
+                feats0.append(out["feat"].clone())
+    rep = level_report(maps)
+    rep["receptive_field_of_u3_px"] = receptive_field(3)
+    rep["u3_covers_p95"] = rep["p95_width_px"] <= receptive_field(3)
+    net = ShadowNet(8, S.U3_SOFT.widths, "f32")
+    net.set_weights(torch.from_numpy(S.he_weights(S.U3_SOFT, seed)))
+    _, rel = sensitivity(net.forward, torch.stack(feats0).contiguous(), repeats=2, seed=seed)
+    names = ["d/f_C", "n.x", "n.y", "n.z", "(z-z_f)/f_L", "z/f_L", "r_e/0.2", "z_blk/f_L"]
+    return {"workload": "soft_train_512 (8 windows x 4 frames)", "penumbra": rep,
+            "sensitivity_rendered_soft8": dict(zip(names, [float(v) for v in rel])),
+            "seconds": time.perf_counter() - t0}
 
 
 def _time_net(torch, nsm, net, feat, vis, steps):
@@ -575,9 +616,10 @@ def main():
     batched = None
     if args.batched:
         batched = batched_section(S, torch, args.seed, reps=20)
-        print(f"[bench] batched: {batched['graph_bf16']['frames_per_s']:.0f} frames/s (graph, bf16) vs "
-              f"{batched['one_by_one_f32']['frames_per_s']:.0f} frames/s (one by one, f32)",
-              file=sys.stderr, flush=True)
+        print(f"[bench] batched: {batched['graph_bf16_tuned']['frames_per_s']:.0f} frames/s (tuned graphs, bf16; "
+              f"{batched['graph_bf16_default']['frames_per_s']:.0f} with default variants) vs "
+              f"{batched['one_by_one_bf16']['frames_per_s']:.0f} (one by one, bf16) and "
+              f"{batched['one_by_one_f32']['frames_per_s']:.0f} (one by one, f32)", file=sys.stderr, flush=True)
     training = None
     if args.training:
         training = training_section(S, torch, args.seed, steps=5)
@@ -589,6 +631,12 @@ def main():
         print(f"[bench] perturbation-loss training step (8 x (1+3) x 512^2, fp32): "
               f"{temporal['perturb_train']['ms_per_step']:.2f} ms; Eq. 3 metric 1080p pair: "
               f"{temporal['metric_1080p']['ms_per_pair'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+    f4 = None
+    if args.f4:
+        f4 = f4_section(S, torch, args.seed)
+        print(f"[bench] penumbra P95 {f4['penumbra']['p95_width_px']:.1f} px over "
+              f"{f4['penumbra']['penumbra_pixels']} penumbra pixels -> {f4['penumbra']['levels']} levels "
+              f"(U3's receptive field {f4['penumbra']['receptive_field_of_u3_px']} px)", file=sys.stderr, flush=True)
     paper_net = None
     if args.paper_net:
         paper_net = paper_net_section(S, torch, args.seed, steps=50)
@@ -608,7 +656,7 @@ def main():
         "network_ms": results[head]["network_ms"],
         "forms": results, "roofline": roof, "roofline_classes": roof_classes, "cpu_baseline": cpu,
         "batched": batched,
-        "paper_net": paper_net, "training": training, "temporal": temporal,
+        "paper_net": paper_net, "training": training, "temporal": temporal, "design_analysis": f4,
     }
     print(json.dumps(line))
     sys.stdout.flush()

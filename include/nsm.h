@@ -65,7 +65,7 @@ typedef enum {
     NSM_E_LAUNCH = 7        /* a kernel launch was rejected                      */
 } nsm_status;
 
-typedef enum { NSM_F32 = 0, NSM_BF16 = 1, NSM_F16 = 2, NSM_F8 = 3 } nsm_dtype;
+typedef enum { NSM_F32 = 0, NSM_BF16 = 1, NSM_F16 = 2, NSM_F8 = 3, NSM_F8_MFMA = 4 } nsm_dtype;
 
 /* Feature sets (channel order, NHWC, float32):
  *   HARD6:  [d/f_C, n.x, n.y, n.z, (z - z_f)/f_L, z/f_L]
@@ -194,7 +194,14 @@ nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n
  * rounded to nearest even), widened to bfloat16 when staged, and computed
  * with bfloat16 weights on bfloat16 MFMA; it halves the activation bytes of
  * NSM_BF16 at E4M3's precision (relative step 1/8).  NSM_ARCH_UNET only
- * (NSM_E_UNSUPPORTED otherwise). */
+ * (NSM_E_UNSUPPORTED otherwise).
+ * NSM_F8_MFMA is the same 8-bit storage with FP8 arithmetic: features are
+ * rounded to E4M3 on load, the 3x3 weights (and the decoders' phase kernels)
+ * to E4M3, the LDS tiles hold E4M3 and the products run on the FP8 MFMA
+ * (v_mfma_f32_16x16x32_fp8_fp8), accumulating in float32; biases, the head
+ * and the sigmoid stay float32.  Its kernels take 16 channels per 16-byte
+ * block, so every stored tensor must have a multiple of 16 channels: the
+ * U-Nets with widths {16, 32, 64} (NSM_E_UNSUPPORTED for {8, 16}). */
 nsm_status nsm_create(const nsm_net_desc *desc, nsm_dtype dtype, nsm_ctx **out);
 nsm_status nsm_destroy(nsm_ctx *ctx);
 
@@ -230,6 +237,32 @@ nsm_status nsm_workspace_bytes(const nsm_ctx *ctx, int n, int h, int w, int trai
  * inspect intermediate tensors; it is fixed for a given ABI version. */
 nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
                        float *logits_out, void *workspace, size_t ws_bytes, void *stream);
+
+/* Launch variants of the NSM_ARCH_UNET forward stages (the batched
+ * multi-frame pipeline's tuning knob).  Each stage can run as one workgroup
+ * per output tile (variant bit 0 clear) or as a persistent grid sized to the
+ * device's resident capacity that strides over the tiles (bit 0 set), with
+ * its default or its alternative tile height (bit 1).  Every variant
+ * computes each output with the same arithmetic in the same order, so all
+ * give the same bits; only the speed differs.
+ *
+ * nsm_autotune times every variant of every stage on the caller's input
+ * (one forward first, so that each stage reads real data; then per stage
+ * and variant one untimed and `reps` timed launches between hipEvents on
+ * `stream`) and keeps the fastest in the context.  It synchronises the
+ * stream, so call it before capturing a graph, never inside one.
+ *   feat      [n][h][w][c_in] float32; vis_out [n][h][w] float32 (scratch
+ *             output of the timed launches); workspace as for nsm_forward.
+ *   reps      1..1000.
+ *   variants_out  host int[number of stages] or NULL: the chosen variants,
+ *             stages in execution order.
+ * nsm_set_stage_variant sets one stage's variant (0..3) by hand;
+ * nsm_get_stage_variants copies up to `max` of them and the stage count.
+ * NSM_E_UNSUPPORTED for the paper's architectures. */
+nsm_status nsm_autotune(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
+                        void *workspace, size_t ws_bytes, int reps, int *variants_out, void *stream);
+nsm_status nsm_set_stage_variant(nsm_ctx *ctx, int stage, int variant);
+nsm_status nsm_get_stage_variants(const nsm_ctx *ctx, int *variants, int max, int *n_stages);
 
 /* nsm_backward -- gradient of sum(dvis * vis) (FP32 NSM_ARCH_UNET contexts):
  * the network's training pass (paper Sec. 3.3 trains the network on

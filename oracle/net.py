@@ -34,7 +34,8 @@ on border pixels and the four phase kernels (bilinear x2 folded into the
 3x3 weights, formed in float64 and rounded once) on interior pixels --
 accumulating in float64.  The 1x1 head keeps float32 weights and reads the
 unrounded last activation.  The 8-bit storage form rounds stored
-activations to FP8 E4M3 and the rest to bfloat16.
+activations to FP8 E4M3 and the rest to bfloat16; the FP8 compute form
+rounds everything the MFMAs read to E4M3 as well.
 """
 import numpy as np
 
@@ -315,9 +316,13 @@ def _head_weights(w):
     return w                       # head weights stay float32
 
 
+def _round_e4m3_via_f32(x):
+    return round_e4m3(np.asarray(x, np.float64).astype(np.float32))
+
+
 def _lowp_types(dtype):
-    cmp = {"bf16": round_bf16, "f16": round_f16, "f8": round_bf16}[dtype]
-    st = round_e4m3 if dtype == "f8" else cmp
+    cmp = {"bf16": round_bf16, "f16": round_f16, "f8": round_bf16, "f8mfma": _round_e4m3_via_f32}[dtype]
+    st = round_e4m3 if dtype in ("f8", "f8mfma") else cmp
     return cmp, st
 
 
@@ -415,7 +420,9 @@ def forward_lowp(c_in, widths, flat, feat, dtype, phase=None, keep=False):
                  decoder activation, then the sigmoid.
 
     dtype 'bf16' / 'f16': compute and storage type alike; 'f8': storage E4M3,
-    compute bfloat16.  Sums are float64.  phase=None computes every decoder
+    compute bfloat16; 'f8mfma': E4M3 for storage and compute (features,
+    weights and phase kernels rounded to E4M3, via float32).  Sums are
+    float64.  phase=None computes every decoder
     pixel in the general form.  keep=True also returns every stored tensor."""
     cmp, st = _lowp_types(dtype)
     phase = phase or {}

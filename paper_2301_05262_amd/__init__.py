@@ -24,6 +24,9 @@ from ._lib import (  # noqa: F401
     frame_params,
     nsm_trace_enable,
     nsm_trace_read,
+    nsm_autotune,
+    nsm_set_stage_variant,
+    nsm_get_stage_variants,
     nsm_perturbation_loss_workspace_bytes,
     nsm_perturbation_loss,
     nsm_perturbation_loss_noalloc,

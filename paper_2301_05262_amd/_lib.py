@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, "libnsm.so")
 NSM_OK = 0
 STATUS_NAMES = {0: "NSM_OK", 1: "NSM_E_INVALID_ARG", 2: "NSM_E_SHAPE", 3: "NSM_E_UNSUPPORTED",
                 4: "NSM_E_WORKSPACE", 5: "NSM_E_NO_WEIGHTS", 6: "NSM_E_DEVICE", 7: "NSM_E_LAUNCH"}
-DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "f8": 3}
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "f8": 3, "f8mfma": 4}
 FEATURE_SETS = {"hard6": 0, "soft8": 1, "paper4": 2}
 FEATURE_CHANNELS = {"hard6": 6, "soft8": 8, "paper4": 4}
 ARCHS = {"unet": 0, "paper": 1, "paper_s2d": 2}
@@ -22,7 +22,8 @@ ARCHS = {"unet": 0, "paper": 1, "paper_s2d": 2}
 EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
     "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
-    "nsm_forward", "nsm_backward", "nsm_trace_enable", "nsm_trace_read",
+    "nsm_forward", "nsm_backward", "nsm_trace_enable", "nsm_trace_read", "nsm_autotune",
+    "nsm_set_stage_variant", "nsm_get_stage_variants",
     "nsm_perturbation_loss_workspace_bytes", "nsm_perturbation_loss", "nsm_perturbation_loss_noalloc",
     "nsm_temporal_workspace_bytes",
     "nsm_temporal_instability",
@@ -80,6 +81,9 @@ def load():
         "nsm_forward": ([vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "nsm_backward": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
         "nsm_trace_enable": ([i32], i32),
+        "nsm_autotune": ([vp, vp, i32, i32, i32, vp, vp, sz, i32, ctypes.POINTER(ctypes.c_int), vp], i32),
+        "nsm_set_stage_variant": ([vp, i32, i32], i32),
+        "nsm_get_stage_variants": ([vp, ctypes.POINTER(ctypes.c_int), i32, ctypes.POINTER(ctypes.c_int)], i32),
         "nsm_perturbation_loss_workspace_bytes": ([i32, i32, i32, i32, psz], i32),
         "nsm_perturbation_loss": ([vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp, sz, vp], i32),
         "nsm_perturbation_loss_noalloc": ([vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp], i32),
@@ -211,6 +215,26 @@ def nsm_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, worksp
     _check(load().nsm_backward(ctx, _ptr(feat), _ptr(dvis), n, h, w, _ptr(dw_out), int(accumulate),
                                _ptr(dfeat_out), _ptr(workspace), ws_bytes, _stream(stream)),
            "nsm_backward")
+
+
+def nsm_autotune(ctx, feat, n, h, w, vis_out, workspace, ws_bytes, reps=5, stream=None):
+    """Times every launch variant of every stage and keeps the fastest;
+    returns the chosen variants (stages in execution order)."""
+    out = (ctypes.c_int * 16)()
+    _check(load().nsm_autotune(ctx, _ptr(feat), n, h, w, _ptr(vis_out), _ptr(workspace), ws_bytes, int(reps),
+                               out, _stream(stream)), "nsm_autotune")
+    return nsm_get_stage_variants(ctx)
+
+
+def nsm_set_stage_variant(ctx, stage, variant):
+    _check(load().nsm_set_stage_variant(ctx, int(stage), int(variant)), "nsm_set_stage_variant")
+
+
+def nsm_get_stage_variants(ctx):
+    out = (ctypes.c_int * 16)()
+    n = ctypes.c_int()
+    _check(load().nsm_get_stage_variants(ctx, out, 16, ctypes.byref(n)), "nsm_get_stage_variants")
+    return [int(out[i]) for i in range(n.value)]
 
 
 def nsm_trace_enable(on=True):

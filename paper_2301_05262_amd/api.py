@@ -123,6 +123,22 @@ class ShadowNet:
         _lib.nsm_forward(self.ctx, feat, n, h, w, vis, lg, ws, ws.numel(), stream)
         return (vis, lg) if logits else vis
 
+    def autotune(self, feat, reps=5, stream=None):
+        """Picks the fastest launch variant of every stage for this input shape
+        (blocking; call before graph capture).  Returns the variants."""
+        if feat.dim() == 3:
+            feat = feat.unsqueeze(0)
+        n, h, w, _ = feat.shape
+        vis = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
+        ws = self.workspace(n, h, w, stream=stream)
+        return _lib.nsm_autotune(self.ctx, feat, n, h, w, vis, ws, ws.numel(), reps, stream)
+
+    def set_variant(self, stage, variant):
+        _lib.nsm_set_stage_variant(self.ctx, stage, variant)
+
+    def variants(self):
+        return _lib.nsm_get_stage_variants(self.ctx)
+
     def backward(self, feat, dvis, dw_out=None, accumulate=False, want_dfeat=True, stream=None):
         if feat.dim() == 3:
             feat = feat.unsqueeze(0)

@@ -1,11 +1,14 @@
-"""Batched multi-frame inference captured in one HIP graph.
+"""Batched multi-frame inference captured in HIP graphs.
 
-Frames of mixed sizes are grouped by resolution; each group's features are
+Frames of mixed sizes are grouped by resolution.  Each group's features are
 built into one [N, H, W, C] tensor (one nsm_build_features call per frame)
-and the network runs once per group (one launch per stage for all frames of
-that size).  The whole sequence is captured into a single graph and replayed.
-The library makes no allocation and no memset inside these calls, so the
-capture holds only kernel nodes.
+and the network runs once per group: one launch per stage for all frames of
+that size, each stage in the launch variant (one workgroup per tile or a
+persistent grid, default or alternative tile height) that nsm_autotune found
+fastest for the group's shape.  Each group is captured into its own graph;
+a batch is the groups' graphs replayed in order, so the frames of a group
+are complete when its graph is.  The library makes no allocation and no
+memset inside these calls, so the captures hold only kernel nodes.
 """
 from collections import OrderedDict
 
@@ -38,31 +41,61 @@ class BatchedPipeline:
                     "sm": torch.empty((S, S), dtype=torch.int32, device=self.device),
                     "gbuf": torch.empty((h, w), dtype=torch.int64, device=self.device),
                 })
-            self.groups.append({"hw": (h, w), "idx": idx, "feat": feat, "vis": vis, "bufs": bufs})
-        self.net = ShadowNet(c_in, widths, dtype, self.device)
-        self.net.set_weights(weights)
-        for g in self.groups:                       # workspaces sized before any capture
-            n = len(g["idx"])
-            self.net.workspace(n, *g["hw"])
-        self.graph = None
+            net = ShadowNet(c_in, widths, dtype, self.device)    # one context per shape: its own variants
+            net.set_weights(weights)
+            net.workspace(len(idx), h, w)                        # sized before any capture
+            self.groups.append({"hw": (h, w), "idx": idx, "feat": feat, "vis": vis, "bufs": bufs, "net": net,
+                                "graph": None, "variants": net.variants()})
+
+    def run_group(self, g):
+        for k, i in enumerate(g["idx"]):
+            self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k])
+        g["net"].forward(g["feat"], vis_out=g["vis"])
 
     def run(self):
-        """Eager pass over all frames (same launches as the graph)."""
+        """Eager pass over all frames (the same launches as the graphs)."""
         for g in self.groups:
-            for k, i in enumerate(g["idx"]):
-                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k])
-            self.net.forward(g["feat"], vis_out=g["vis"])
+            self.run_group(g)
 
-    def capture(self):
-        self.run()                                  # warm-up: every workspace exists
+    def autotune(self, reps=5):
+        """Fastest launch variant per stage for every group (blocking)."""
+        self.run()
         torch.cuda.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            self.run()
+        for g in self.groups:
+            g["variants"] = g["net"].autotune(g["feat"], reps=reps)
+        return [g["variants"] for g in self.groups]
+
+    def capture(self, tune=True):
+        if tune:
+            self.autotune()
+        self.run()                                  # warm-up: every workspace and variant is set up
+        torch.cuda.synchronize()
+        for g in self.groups:
+            g["graph"] = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g["graph"]):
+                self.run_group(g)
         torch.cuda.synchronize()
 
     def replay(self):
-        self.graph.replay()
+        for g in self.groups:
+            g["graph"].replay()
+
+    def replay_timed(self):
+        """Replays one batch; returns (batch ms, [completion ms of every frame
+        since the batch started], input order)."""
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ends = [torch.cuda.Event(enable_timing=True) for _ in self.groups]
+        ev0.record()
+        for g, e in zip(self.groups, ends):
+            g["graph"].replay()
+            e.record()
+        ends[-1].synchronize()
+        done = [0.0] * len(self.frames)
+        for g, e in zip(self.groups, ends):
+            t = ev0.elapsed_time(e)
+            for i in g["idx"]:
+                done[i] = t
+        return ev0.elapsed_time(ends[-1]), done
 
     def visibility(self):
         """[(frame index, vis [H, W])] in input order."""

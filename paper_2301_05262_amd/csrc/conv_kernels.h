@@ -53,11 +53,14 @@ template <> struct DT<Dt::F8> { using T = __bf16; static constexpr int EPB = 8; 
 struct e4m3 {
     unsigned char bits;
 };
+// FP8 compute form: E4M3 in LDS and in the MFMAs, a block holds 16 values.
+template <> struct DT<Dt::F8M> { using T = e4m3; static constexpr int EPB = 16; };
 
 // Storage type of activations in global memory: the compute type, except
 // for the 8-bit storage form.
 template <Dt D> struct ST { using S = typename DT<D>::T; };
 template <> struct ST<Dt::F8> { using S = e4m3; };
+template <> struct ST<Dt::F8M> { using S = e4m3; };
 
 constexpr int kThreads = 256;
 constexpr int kTW = 32;   // tile width: two 16-pixel MFMA column fragments
@@ -103,6 +106,7 @@ struct Geo {
 __device__ __forceinline__ float to_f(float v) { return v; }
 __device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
 __device__ __forceinline__ float to_f(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(e4m3 v) { return __builtin_amdgcn_cvt_f32_fp8((int)v.bits, 0); }
 
 template <typename T> __device__ __forceinline__ T from_f(float v);
 template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
@@ -149,6 +153,13 @@ __device__ __forceinline__ f32x4 mfma_kgroup(const u32x4& wa, const u32x4& xb, f
     } else if constexpr (D == Dt::BF16 || D == Dt::F8) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, wa),
                                                       __builtin_bit_cast(bf16x8, xb), acc, 0, 0, 0);
+    } else if constexpr (D == Dt::F8M) {
+        // a block of 16 E4M3 values feeds two K = 32 FP8 MFMAs: bytes 0-7 of
+        // every lane group, then bytes 8-15 (weights and pixels split alike)
+        const long a0 = (long)(((unsigned long)wa[1] << 32) | wa[0]), a1 = (long)(((unsigned long)wa[3] << 32) | wa[2]);
+        const long b0 = (long)(((unsigned long)xb[1] << 32) | xb[0]), b1 = (long)(((unsigned long)xb[3] << 32) | xb[2]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
     } else {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, wa),
                                                      __builtin_bit_cast(f16x8, xb), acc, 0, 0, 0);
@@ -161,6 +172,8 @@ template <Dt D>
 __device__ __forceinline__ u32x4 pack_block(const float* v) {
     using T = typename DT<D>::T;
     constexpr int EPB = DT<D>::EPB;
+    if constexpr (D == Dt::F8M)
+        return u32x4{pack4_e4m3(v), pack4_e4m3(v + 4), pack4_e4m3(v + 8), pack4_e4m3(v + 12)};
     T t[EPB];
 #pragma unroll
     for (int e = 0; e < EPB; ++e) t[e] = from_f<T>(v[e]);
@@ -762,6 +775,24 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3(ConvArgs a) {
     const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
     conv_tile<D, IN_F32, CS, CU, CO, MODE, TH>(a, (lt % gx) * kTW, ((lt / gx) % gy) * TH, lt / (gx * gy), smem,
                                                smem + GT::LOW_OFF);
+}
+
+// Persistent form of k_conv3x3: a grid sized to the resident capacity of the
+// device (a multiple of 8, so that block b stays on XCD b % 8) walks the
+// gx x gy x n tiles with a stride of the grid; the per-tile work and its
+// arithmetic are those of k_conv3x3, so both give the same bits.
+template <Dt D, bool IN_F32, int CS, int CU, int CO, OutMode MODE, int TH>
+__global__ void __launch_bounds__(kThreads) k_conv3x3_persist(ConvArgs a, int gx, int gy) {
+    using T = typename DT<D>::T;
+    using GT = GenTile<D, CS, CU, CO, TH>;
+    __shared__ __attribute__((aligned(16))) T smem[GT::ELEMS];
+    const int total = gx * gy * a.n;
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        if (b != (int)blockIdx.x) __syncthreads();     // the previous tile's LDS reads are done
+        const int lt = xcd_remap(b, total);
+        conv_tile<D, IN_F32, CS, CU, CO, MODE, TH>(a, (lt % gx) * kTW, ((lt / gx) % gy) * TH, lt / (gx * gy), smem,
+                                                   smem + GT::LOW_OFF);
+    }
 }
 
 // Weight repack: OHWI float32 [CO][3][3][CS+CU] -> [NF][NKG][64 lanes][EPB]

@@ -131,8 +131,18 @@ __global__ void k_pack_up(const float* __restrict__ w, void* __restrict__ out) {
 // interior TH x 32 tiles, none of whose pixels lies in the first or last row
 // or column.  Border blocks come first so that their slower general path
 // overlaps the phase-form blocks.  MODE is Store or Head.
+template <Dt D, int CS, int CU, int CO, int TH, int TH_G>
+constexpr int up_smem_elems() {
+    using UT = UpTile<D, CS, CU, TH>;
+    using GT = GenTile<D, CS, CU, CO, TH_G>;
+    constexpr int LOW_OFF = (UT::SKIP + 7) / 8 * 8;
+    return (LOW_OFF + UT::LOW) > GT::ELEMS ? (LOW_OFF + UT::LOW) : GT::ELEMS;
+}
+
+// Logical block b of a decoder stage (border tiles first, then interior).
 template <Dt D, int CS, int CU, int CO, OutMode MODE, int TH, int TH_G>
-__global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void* __restrict__ wup) {
+__device__ __forceinline__ void up_block(const ConvArgs& a, const void* __restrict__ wup, int b,
+                                         typename DT<D>::T* smem) {
     using T = typename DT<D>::T;
     using G = UpGeo<D, CS, CU, CO>;
     using UT = UpTile<D, CS, CU, TH>;
@@ -142,22 +152,19 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
     static_assert(TH % 8 == 0 && TH % TH_G == 0, "each wave needs rows of one parity in one half of the tile");
     static_assert(MODE == OutMode::Store || MODE == OutMode::Head, "decoder stages store or end in the head");
     constexpr int LOW_OFF = (UT::SKIP + 7) / 8 * 8;
-    constexpr int ELEMS = (LOW_OFF + UT::LOW) > GT::ELEMS ? (LOW_OFF + UT::LOW) : GT::ELEMS;
-
-    __shared__ __attribute__((aligned(16))) T smem[ELEMS];
 
     const int h = a.h, w = a.w, hl = h >> 1, wl = w >> 1;
     const int nb = border_tiles_per_image(TH, TH_G, h, w) * a.n;
-    if ((int)blockIdx.x < nb) {
+    if (b < nb) {
         int bx, by, bn;
-        border_tile(blockIdx.x, TH, TH_G, h, w, &bx, &by, &bn);
+        border_tile(b, TH, TH_G, h, w, &bx, &by, &bn);
         conv_tile<D, false, CS, CU, CO, MODE, TH_G>(a, bx, by, bn, smem, smem + GT::LOW_OFF);
         return;
     }
     T* skip = smem;
     T* lowt = smem + LOW_OFF;
     const int gx = (w + kTW - 1) / kTW - 2, gy = (h + TH - 1) / TH - 2;
-    const int lt = xcd_remap(blockIdx.x - nb, gx * gy * a.n);
+    const int lt = xcd_remap(b - nb, gx * gy * a.n);
     const int x0 = (lt % gx + 1) * kTW, y0 = ((lt / gx) % gy + 1) * TH, n = lt / (gx * gy);
 
     // ---------------- prologue: skip tile (split by column parity) and low tile
@@ -359,6 +366,25 @@ __global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void*
 #pragma unroll
                 for (int f = 0; f < NFW; ++f)
                     buf_store4<S>(orc, voff, m * rstep + (p * CO + (f0 + f) * 16) * SZ, acc[m][p][f]);
+    }
+}
+
+template <Dt D, int CS, int CU, int CO, OutMode MODE, int TH, int TH_G>
+__global__ void __launch_bounds__(kThreads) k_conv3x3_up(ConvArgs a, const void* __restrict__ wup) {
+    using T = typename DT<D>::T;
+    __shared__ __attribute__((aligned(16))) T smem[up_smem_elems<D, CS, CU, CO, TH, TH_G>()];
+    up_block<D, CS, CU, CO, MODE, TH, TH_G>(a, wup, blockIdx.x, smem);
+}
+
+// Persistent form: a grid sized to the device's resident capacity walks the
+// stage's logical blocks with a stride of the grid (same tiles, same bits).
+template <Dt D, int CS, int CU, int CO, OutMode MODE, int TH, int TH_G>
+__global__ void __launch_bounds__(kThreads) k_conv3x3_up_persist(ConvArgs a, const void* __restrict__ wup, int total) {
+    using T = typename DT<D>::T;
+    __shared__ __attribute__((aligned(16))) T smem[up_smem_elems<D, CS, CU, CO, TH, TH_G>()];
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        if (b != (int)blockIdx.x) __syncthreads();     // the previous block's LDS reads are done
+        up_block<D, CS, CU, CO, MODE, TH, TH_G>(a, wup, b, smem);
     }
 }
 

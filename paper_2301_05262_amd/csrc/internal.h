@@ -109,8 +109,9 @@ hipError_t temporal_pair(const float* tris, const float* normals, int n_tris, co
 
 // --------------------------------------------------------------- network
 // F8: 8-bit temporary storage -- activations stored in global memory as FP8
-// E4M3 (OCP), weights and compute in bfloat16.
-enum class Dt { F32 = 0, BF16 = 1, F16 = 2, F8 = 3 };
+// E4M3 (OCP), weights and compute in bfloat16.  F8M: FP8 E4M3 throughout --
+// stored activations, LDS tiles and weights -- on the FP8 MFMA.
+enum class Dt { F32 = 0, BF16 = 1, F16 = 2, F8 = 3, F8M = 4 };
 
 // One 3x3 conv stage as the kernels see it.
 struct ConvStage {
@@ -141,7 +142,11 @@ struct ConvArgs {
     int n, h, w;
     bool in_f32;
 };
-hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs& a, hipStream_t s);
+// variant 0..3: bit 0 the persistent grid, bit 1 the stage's alternative tile
+// rows; all variants give the same bits.
+constexpr int kConvVariants = 4;
+hipError_t conv_forward(const ConvStage& st, Dt dt, OutMode mode, const ConvArgs& a, hipStream_t s,
+                        int variant = 0);
 bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32);
 
 // ---------------------------------------------- the paper's network (P-net)

@@ -58,6 +58,7 @@ struct nsm_ctx {
     size_t flat_off = 0;             // byte offset of the float32 flat copy
     bool has_weights = false;
     bool trainable = false;          // FP32 context with backward kernels for every stage
+    int variant[16] = {};            // launch variant per stage (NSM_ARCH_UNET): see conv_forward
 };
 
 extern "C" {
@@ -151,11 +152,13 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
 nsm_status nsm_create(const nsm_net_desc* desc, nsm_dtype dtype, nsm_ctx** out) {
     if (!desc || !out) return NSM_E_INVALID_ARG;
     *out = nullptr;
-    if (dtype != NSM_F32 && dtype != NSM_BF16 && dtype != NSM_F16 && dtype != NSM_F8) return NSM_E_INVALID_ARG;
+    if (dtype != NSM_F32 && dtype != NSM_BF16 && dtype != NSM_F16 && dtype != NSM_F8 && dtype != NSM_F8_MFMA)
+        return NSM_E_INVALID_ARG;
     const int L = desc->levels;
     if (L < 2 || L > 5 || desc->c_in < 1) return NSM_E_UNSUPPORTED;
     if (desc->arch == NSM_ARCH_UNET && L > 4) return NSM_E_UNSUPPORTED;
-    if (desc->arch != NSM_ARCH_UNET && dtype == NSM_F8) return NSM_E_UNSUPPORTED;   // 8-bit storage: U-Net only
+    if (desc->arch != NSM_ARCH_UNET && (dtype == NSM_F8 || dtype == NSM_F8_MFMA))
+        return NSM_E_UNSUPPORTED;   // 8-bit forms: U-Net only
     for (int l = 0; l < L; ++l)
         if (desc->widths[l] < 1) return NSM_E_UNSUPPORTED;
     if (desc->arch != NSM_ARCH_UNET && desc->arch != NSM_ARCH_PAPER && desc->arch != NSM_ARCH_PAPER_S2D)
@@ -325,7 +328,7 @@ struct FwdLayout {
 };
 
 // bytes of one stored activation
-size_t elem_size(Dt dt) { return dt == Dt::F32 ? 4 : (dt == Dt::F8 ? 1 : 2); }
+size_t elem_size(Dt dt) { return dt == Dt::F32 ? 4 : ((dt == Dt::F8 || dt == Dt::F8M) ? 1 : 2); }
 
 FwdLayout plan_forward(const nsm_ctx* c, int n, int h, int w, bool training) {
     FwdLayout L{};
@@ -435,14 +438,16 @@ nsm_status check_net_shape(const nsm_ctx* c, int n, int h, int w) {
     return NSM_OK;
 }
 
-// Enqueue the forward pass; `act_out` (float32 [n][h][w][w0]) receives the
-// last decoder activation when non-null (training).
-hipError_t run_forward(const nsm_ctx* c, const float* feat, int n, int h, int w, float* vis,
-                       float* logits, char* ws, const FwdLayout& L, float* act_out, hipStream_t s) {
+// The arguments of every stage of the forward pass; `act_out` (float32
+// [n][h][w][w0]) receives the last decoder activation when non-null
+// (training).
+std::vector<ConvArgs> forward_args(const nsm_ctx* c, const float* feat, int n, int h, int w, float* vis,
+                                   float* logits, char* ws, const FwdLayout& L, float* act_out) {
     const char* base = reinterpret_cast<const char*>(c->dbuf);
     const float* flat = reinterpret_cast<const float*>(base + c->flat_off);
     const int lv = c->desc.levels;
     const void* prev = feat;          // input of the next encoder stage
+    std::vector<ConvArgs> out;
     for (const auto& p : c->stages) {
         ConvArgs a{};
         a.wpk = base + p.pk_off;
@@ -472,7 +477,18 @@ hipError_t run_forward(const nsm_ctx* c, const float* feat, int n, int h, int w,
                 a.out = ws + L.dec[l];
             }
         }
-        hipError_t e = conv_forward(p.st, c->dt, p.mode, a, s);
+        out.push_back(a);
+    }
+    return out;
+}
+
+// Enqueue the forward pass with the context's launch variants.
+hipError_t run_forward(const nsm_ctx* c, const float* feat, int n, int h, int w, float* vis,
+                       float* logits, char* ws, const FwdLayout& L, float* act_out, hipStream_t s) {
+    const std::vector<ConvArgs> args = forward_args(c, feat, n, h, w, vis, logits, ws, L, act_out);
+    for (size_t i = 0; i < c->stages.size(); ++i) {
+        const StagePlan& p = c->stages[i];
+        hipError_t e = conv_forward(p.st, c->dt, p.mode, args[i], s, c->variant[i]);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -610,6 +626,77 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
                                : run_forward(ctx, feat, n, h, w, vis_out, logits_out, ws, L, nullptr, s);
     if (e != hipSuccess) return NSM_E_LAUNCH;
     if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
+    return NSM_OK;
+}
+
+nsm_status nsm_autotune(nsm_ctx* ctx, const float* feat, int n, int h, int w, float* vis_out, void* workspace,
+                        size_t ws_bytes, int reps, int* variants_out, void* stream) {
+    if (!ctx || !feat || !vis_out || reps < 1 || reps > 1000) return NSM_E_INVALID_ARG;
+    if (ctx->desc.arch != NSM_ARCH_UNET) return NSM_E_UNSUPPORTED;
+    nsm_status st = check_net_shape(ctx, n, h, w);
+    if (st != NSM_OK) return st;
+    if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
+    const FwdLayout L = plan_forward(ctx, n, h, w, false);
+    if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
+    if (!device_ok()) return NSM_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    // one forward with the current variants leaves every stage's input in the workspace
+    if (run_forward(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr, s) != hipSuccess) return NSM_E_LAUNCH;
+    const std::vector<ConvArgs> args = forward_args(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return NSM_E_DEVICE;
+    }
+    nsm_status res = NSM_OK;
+    for (size_t i = 0; i < ctx->stages.size() && res == NSM_OK; ++i) {
+        const StagePlan& p = ctx->stages[i];
+        float best = 0.0f;
+        int pick = ctx->variant[i];
+        for (int v = 0; v < kConvVariants && res == NSM_OK; ++v) {
+            // one untimed launch (first-use set-up of the variant), then `reps` timed ones
+            if (conv_forward(p.st, ctx->dt, p.mode, args[i], s, v) != hipSuccess ||
+                hipEventRecord(e0, s) != hipSuccess) {
+                res = NSM_E_LAUNCH;
+                break;
+            }
+            for (int r = 0; r < reps; ++r)
+                if (conv_forward(p.st, ctx->dt, p.mode, args[i], s, v) != hipSuccess) res = NSM_E_LAUNCH;
+            float ms = 0.0f;
+            if (res != NSM_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                res = res == NSM_OK ? NSM_E_DEVICE : res;
+                break;
+            }
+            if (v == 0 || ms < best) {
+                best = ms;
+                pick = v;
+            }
+        }
+        ctx->variant[i] = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (res != NSM_OK) return res;
+    if (variants_out)
+        for (size_t i = 0; i < ctx->stages.size(); ++i) variants_out[i] = ctx->variant[i];
+    return NSM_OK;
+}
+
+nsm_status nsm_set_stage_variant(nsm_ctx* ctx, int stage, int variant) {
+    if (!ctx || variant < 0 || variant >= kConvVariants) return NSM_E_INVALID_ARG;
+    if (ctx->desc.arch != NSM_ARCH_UNET) return NSM_E_UNSUPPORTED;
+    if (stage < 0 || stage >= (int)ctx->stages.size()) return NSM_E_INVALID_ARG;
+    ctx->variant[stage] = variant;
+    return NSM_OK;
+}
+
+nsm_status nsm_get_stage_variants(const nsm_ctx* ctx, int* variants, int max, int* n_stages) {
+    if (!ctx || !n_stages || max < 0 || (max > 0 && !variants)) return NSM_E_INVALID_ARG;
+    const int ns = (int)ctx->stages.size();
+    *n_stages = ns;
+    for (int i = 0; i < ns && i < max; ++i) variants[i] = ctx->variant[i];
     return NSM_OK;
 }
 

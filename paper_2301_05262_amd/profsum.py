@@ -26,6 +26,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CALIB_BYTES = 256 << 20          # the calibration copy: 256 MiB read, 256 MiB written
+SIMDS_PER_SE = 32                # MI355X: 256 CUs in 32 shader engines, 4 SIMDs per CU
 TRAFFIC_TAG = "traffic-json:"
 
 
@@ -61,7 +62,7 @@ def _strip_args(k):
 def short_name(k):
     """Kernel symbol -> readable name with template arguments."""
     k = _strip_args(k)
-    k = re.sub(r"\(nsm::Dt\)(\d)", lambda m: ["f32", "bf16", "f16"][int(m.group(1))], k)
+    k = re.sub(r"\(nsm::Dt\)(\d)", lambda m: ["f32", "bf16", "f16", "f8", "f8mfma"][int(m.group(1))], k)
     k = re.sub(r"\(nsm::OutMode\)(\d)", lambda m: ["Store", "Pool", "Head", "Linear"][int(m.group(1))], k)
     k = re.sub(r"\(nsm::PMode\)(\d)", lambda m: ["Store", "PoolOnly", "PoolSkip", "Head"][int(m.group(1))], k)
     k = k.replace("nsm::(anonymous namespace)::", "").replace("nsm::ck::", "").replace("nsm::", "")
@@ -138,6 +139,11 @@ def counters_table(dirs, title="counters"):
             out.append(f"- per wave ({waves:.0f} waves sampled): " + ", ".join(per))
         rest = [f"{c} {m[c]:.4g}" for c in sorted(m) if not c.startswith("SQ_INSTS_") and c != "SQ_WAVES"]
         out.append("- " + ", ".join(rest))
+        if m.get("SQ_VALU_MFMA_BUSY_CYCLES") and m.get("SQ_BUSY_CYCLES"):
+            r = m["SQ_VALU_MFMA_BUSY_CYCLES"] / m["SQ_BUSY_CYCLES"]
+            out.append(f"- MFMA busy: SQ_VALU_MFMA_BUSY_CYCLES / SQ_BUSY_CYCLES = {r:.2f} SIMD-cycles per "
+                       f"shader-engine busy cycle, i.e. {100 * r / SIMDS_PER_SE:.0f}% of the "
+                       f"{SIMDS_PER_SE} SIMDs of a shader engine")
         out.append("")
     return "\n".join(out)
 

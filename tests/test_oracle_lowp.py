@@ -64,8 +64,8 @@ def test_phase_conv_equals_upsampled_conv_away_from_border():
 # ------------------------------------------------- scalar reference of the form
 def _cast(x, dtype, storage):
     t = torch.from_numpy(np.asarray(x, np.float64))
-    if dtype == "f8" and storage:
-        return t.clamp(-448.0, 448.0).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    if (dtype == "f8" and storage) or dtype == "f8mfma":
+        return t.to(torch.float32).clamp(-448.0, 448.0).to(torch.float8_e4m3fn).to(torch.float64).numpy()
     tt = torch.float16 if dtype == "f16" else torch.bfloat16
     return t.to(torch.float32).to(tt).to(torch.float64).numpy()
 
@@ -231,7 +231,7 @@ def _mismatches(name, desc, hw, boxes, dtype):
     return bad
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f16", "f8"])
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f8", "f8mfma"])
 @pytest.mark.parametrize("name,desc,hw,boxes", CASES)
 def test_forward_lowp_equals_scalar_reference(name, desc, hw, boxes, dtype):
     assert _mismatches(name, desc, hw, boxes, dtype) == []
