@@ -221,8 +221,8 @@ def batched_section(S, torch, seed, reps):
 def training_section(S, torch, seed, steps):
     """One training step of the soft-shadow net (FP32, the differentiation
     form) on 8 windows x 4 frames of 512x512: SOFT8 features of all 32 frames,
-    forward, MSE loss gradient, backward with recomputed activations (dW and
-    dfeatures).  Targets are fixed synthetic visibilities in [0, 1] (the
+    forward keeping its activations, MSE loss gradient, backward from those
+    activations (dW and dfeatures).  Targets are fixed synthetic visibilities in [0, 1] (the
     64-sample ray-cast targets are data generation, not part of a step)."""
     from paper_2301_05262_amd.api import FeatureBuilder, ShadowNet
     wins = [S.make_train_window(seed, k) for k in range(8)]
@@ -231,6 +231,8 @@ def training_section(S, torch, seed, steps):
     n = len(frames)
     feat = torch.empty((n, 512, 512, 8), dtype=torch.float32, device="cuda")
     bufs = [b(fr, soft=True) for b, fr in frames]
+    for k in range(n):
+        bufs[k]["feat"] = feat[k]          # each frame's features land in the batch directly
     rng = S.SplitMix64(seed + 7)
     target = torch.from_numpy(rng.uniforms(n * 512 * 512, 0.0, 1.0).reshape(n, 512, 512).astype(np.float32)).cuda()
     net = ShadowNet(8, S.U3_SOFT.widths, "f32")
@@ -240,10 +242,9 @@ def training_section(S, torch, seed, steps):
     def step():
         for k, (b, fr) in enumerate(frames):
             b(fr, soft=True, out=bufs[k])
-            feat[k].copy_(bufs[k]["feat"])
-        vis = net.forward(feat)
+        vis = net.forward_train(feat)
         dvis = (2.0 / vis.numel()) * (vis - target)
-        net.backward(feat, dvis, dw_out=dw)
+        net.backward(feat, dvis, dw_out=dw, saved=True)
 
     for _ in range(2):
         step()
@@ -258,7 +259,7 @@ def training_section(S, torch, seed, steps):
     w0, w1, w2 = S.U3_SOFT.widths
     L0, L1, L2 = 512 * 512, 256 * 256, 128 * 128
     macs = 9 * (L0 * w0 * 8 + L1 * w1 * w0 + L2 * w2 * w1 + L1 * w1 * (w1 + w2) + L0 * w0 * (w0 + w1)) + L0 * w0
-    flop = 2.0 * macs * n * 4        # forward + recomputed forward + two backward GEMMs per conv
+    flop = 2.0 * macs * n * 3        # forward + two backward GEMMs per conv
     return {"workload": "soft_train_512", "frames": n, "ms_per_step": ms, "dtype": "f32",
             "tflops_effective": flop / (ms * 1e-3) / 1e12, "flop_per_step": flop,
             "ideal_ms_at_fp32_mfma_peak": flop / MFMA_PEAK["f32"] * 1e3}

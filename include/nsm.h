@@ -12,7 +12,9 @@
  *   nsm_build_features  light-view z-buffer, camera G-buffer, feature gather
  *   nsm_forward         U-Net inference (FP32, or BF16/FP16 on MFMA)
  *   nsm_backward        gradient of the visibility w.r.t. the weights and
- *                       the features (the differentiation form; FP32)
+ *                       the features (the differentiation form; FP32;
+ *                       nsm_forward_train + nsm_backward_saved split it
+ *                       around the loss without recomputing the forward)
  * and two around it for temporal stability:
  *   nsm_perturbation_loss     Eq. 2's loss and its gradient through x_0
  *   nsm_temporal_instability  Eq. 3's metric over a pair of frames
@@ -284,6 +286,27 @@ nsm_status nsm_get_stage_variants(const nsm_ctx *ctx, int *variants, int max, in
 nsm_status nsm_backward(nsm_ctx *ctx, const float *feat, const float *dvis, int n, int h, int w,
                         float *dw_out, int accumulate, float *dfeat_out, void *workspace,
                         size_t ws_bytes, void *stream);
+
+/* nsm_forward_train / nsm_backward_saved -- the same training pass without
+ * the recomputed forward: backpropagation reuses the forward's activations
+ * (paper Sec. 3.3 trains by gradient descent; this pair only moves where the
+ * activations come from).  nsm_forward_train runs the FP32 forward with the
+ * training workspace (nsm_workspace_bytes with training = 1), keeps every
+ * activation there and copies the visibility to vis_out ([n][h][w] float32,
+ * or NULL); its visibility is the same bits as nsm_forward's.
+ * nsm_backward_saved then computes what nsm_backward computes, the same bits,
+ * from those activations.  It requires that the last call on this context
+ * that used a workspace was nsm_forward_train or nsm_backward (either
+ * flavour) with the same workspace, feature pointer, n, h and w, and that
+ * nsm_set_weights has not been called since; otherwise it returns
+ * NSM_E_INVALID_ARG and enqueues nothing.  The caller must not modify the
+ * workspace or the features in between (the library cannot check that).
+ * nsm_forward, nsm_autotune and nsm_set_weights forget the saved forward. */
+nsm_status nsm_forward_train(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
+                             void *workspace, size_t ws_bytes, void *stream);
+nsm_status nsm_backward_saved(nsm_ctx *ctx, const float *feat, const float *dvis, int n, int h, int w,
+                              float *dw_out, int accumulate, float *dfeat_out, void *workspace,
+                              size_t ws_bytes, void *stream);
 
 /* --------------------------------------------------- temporal stability
  * nsm_perturbation_loss -- the perturbation loss of paper Sec. 3.3, Eq. 2,

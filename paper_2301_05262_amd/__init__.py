@@ -21,6 +21,8 @@ from ._lib import (  # noqa: F401
     nsm_workspace_bytes,
     nsm_forward,
     nsm_backward,
+    nsm_forward_train,
+    nsm_backward_saved,
     frame_params,
     nsm_trace_enable,
     nsm_trace_read,

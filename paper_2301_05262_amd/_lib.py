@@ -22,7 +22,7 @@ ARCHS = {"unet": 0, "paper": 1, "paper_s2d": 2}
 EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
     "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
-    "nsm_forward", "nsm_backward", "nsm_trace_enable", "nsm_trace_read", "nsm_autotune",
+    "nsm_forward", "nsm_backward", "nsm_forward_train", "nsm_backward_saved", "nsm_trace_enable", "nsm_trace_read", "nsm_autotune",
     "nsm_set_stage_variant", "nsm_get_stage_variants",
     "nsm_perturbation_loss_workspace_bytes", "nsm_perturbation_loss", "nsm_perturbation_loss_noalloc",
     "nsm_temporal_workspace_bytes",
@@ -80,6 +80,8 @@ def load():
         "nsm_workspace_bytes": ([vp, i32, i32, i32, i32, psz], i32),
         "nsm_forward": ([vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "nsm_backward": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+        "nsm_forward_train": ([vp, vp, i32, i32, i32, vp, vp, sz, vp], i32),
+        "nsm_backward_saved": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
         "nsm_trace_enable": ([i32], i32),
         "nsm_autotune": ([vp, vp, i32, i32, i32, vp, vp, sz, i32, ctypes.POINTER(ctypes.c_int), vp], i32),
         "nsm_set_stage_variant": ([vp, i32, i32], i32),
@@ -215,6 +217,18 @@ def nsm_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, worksp
     _check(load().nsm_backward(ctx, _ptr(feat), _ptr(dvis), n, h, w, _ptr(dw_out), int(accumulate),
                                _ptr(dfeat_out), _ptr(workspace), ws_bytes, _stream(stream)),
            "nsm_backward")
+
+
+def nsm_forward_train(ctx, feat, n, h, w, vis_out, workspace, ws_bytes, stream=None):
+    _check(load().nsm_forward_train(ctx, _ptr(feat), n, h, w, _ptr(vis_out), _ptr(workspace), ws_bytes,
+                                    _stream(stream)), "nsm_forward_train")
+
+
+def nsm_backward_saved(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, workspace, ws_bytes,
+                       stream=None):
+    _check(load().nsm_backward_saved(ctx, _ptr(feat), _ptr(dvis), n, h, w, _ptr(dw_out), int(accumulate),
+                                     _ptr(dfeat_out), _ptr(workspace), ws_bytes, _stream(stream)),
+           "nsm_backward_saved")
 
 
 def nsm_autotune(ctx, feat, n, h, w, vis_out, workspace, ws_bytes, reps=5, stream=None):

@@ -139,7 +139,23 @@ class ShadowNet:
     def variants(self):
         return _lib.nsm_get_stage_variants(self.ctx)
 
-    def backward(self, feat, dvis, dw_out=None, accumulate=False, want_dfeat=True, stream=None):
+    def forward_train(self, feat, vis_out=None, stream=None):
+        """FP32 forward that keeps every activation in the training workspace
+        for a following backward(..., saved=True) on the same features."""
+        if feat.dim() == 3:
+            feat = feat.unsqueeze(0)
+        n, h, w, c = feat.shape
+        if c != self.c_in or feat.dtype != torch.float32 or not feat.is_contiguous():
+            raise ValueError("features must be contiguous float32 [N,H,W,c_in]")
+        vis = vis_out if vis_out is not None else torch.empty((n, h, w), dtype=torch.float32,
+                                                              device=feat.device)
+        ws = self.workspace(n, h, w, training=True, stream=stream)
+        _lib.nsm_forward_train(self.ctx, feat, n, h, w, vis, ws, ws.numel(), stream)
+        return vis
+
+    def backward(self, feat, dvis, dw_out=None, accumulate=False, want_dfeat=True, saved=False, stream=None):
+        """saved=True reuses the activations of the last forward_train (or
+        backward) on the same features instead of recomputing them."""
         if feat.dim() == 3:
             feat = feat.unsqueeze(0)
         n, h, w, c = feat.shape
@@ -148,8 +164,8 @@ class ShadowNet:
                                                            device=feat.device)
         df = torch.empty_like(feat) if want_dfeat else None
         ws = self.workspace(n, h, w, training=True, stream=stream)
-        _lib.nsm_backward(self.ctx, feat, dvis, n, h, w, dw, int(accumulate), df, ws, ws.numel(),
-                          stream)
+        call = _lib.nsm_backward_saved if saved else _lib.nsm_backward
+        call(self.ctx, feat, dvis, n, h, w, dw, int(accumulate), df, ws, ws.numel(), stream)
         return dw, df
 
 

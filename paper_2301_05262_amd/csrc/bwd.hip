@@ -12,7 +12,7 @@
 //   wgrad      dW[co][tap][ci] = sum_p dz[p][co] * x[p + tap][ci] and
 //              db[co] = sum_p dz[p][co]: an MFMA GEMM with the pixels as K;
 //              every block owns a fixed run of tiles and writes its partial
-//              sums, which a second kernel adds in block order -- no float
+//              sums, which a second kernel adds in a fixed order -- no float
 //              atomics, so the result is bitwise reproducible;
 //   upsample   adjoint of the bilinear x2 upsampling written as a gather:
 //              each low-res pixel sums the hi-res gradients that its taps
@@ -31,7 +31,6 @@ namespace {
 using namespace ck;
 
 constexpr int kHeadGrid = 1024;
-constexpr int kWgradMaxGrid = 512;
 constexpr int kWTH = 4;                          // wgrad tile rows (x 32 columns)
 
 // ------------------------------------------------------------------- head
@@ -187,18 +186,40 @@ __global__ void __launch_bounds__(256) k_pool_transpose_mask(const float* __rest
 }
 
 // ------------------------------------------------------------------ wgrad
+// GEMM dW[co][j] = sum_p dz[p][co] X[p][j] over the pixels p, with column
+// j = tap * CIP + ci (CIP = channels, the skip part padded to 4) and one more
+// column of ones for the bias.  MFMA 16x16x4 f32: A = dz (16 output channels
+// x 4 pixels), B = X (4 pixels x 16 columns).  Columns go in groups of 64:
+// lane (n, g) of MFMA i of a group covers column 64 grp + 4 n + i, so one
+// 16-byte LDS read (channels ci .. ci + 3 of one tap, 16-byte aligned) feeds
+// the four MFMAs of the group.  Each wave owns one 16-row output fragment.
+// When the groups divide evenly among the WPF waves of a fragment, each wave
+// takes every WPF-th group over all pixels; otherwise each wave takes all
+// groups over every WPF-th step of 4 pixels, and the waves' sums are added
+// in a fixed order at the end.  Either way the waves' MFMA work is balanced
+// and every result is reproducible bit for bit.
 template <int CS, int CU, int CO>
 struct WG {
     static constexpr int CSP = round_up(CS, 4);
     static constexpr int CIP = CSP + CU;
     static constexpr int CST = lds_stride<Dt::F32>(CIP);
     static constexpr int NCOL = 9 * CIP;
-    static constexpr int NCOLP = round_up(NCOL, 16) + 16;     // + one bias block
-    static constexpr int NFCOL = NCOLP / 16;
+    static constexpr int NCOLP = round_up(NCOL + 16, 64);    // bias column at NCOLP - 16
+    static constexpr int NG = NCOLP / 64;                     // column groups
     static constexpr int NFCO = (CO + 15) / 16;
     static constexpr int COP = NFCO * 16;
-    static constexpr int FPW = (NFCOL + 3) / 4;               // column fragments per wave
-    static constexpr int PARTIAL = COP * NCOLP;                // floats per block
+    static constexpr int WPF = 4 / NFCO;                      // waves per output fragment
+    static constexpr bool BY_GROUP = NG % WPF == 0;
+    static constexpr int PS = BY_GROUP ? 1 : WPF;             // waves splitting the pixel steps
+    static constexpr int UPW = BY_GROUP ? NG / WPF : NG;      // groups per wave
+    static constexpr int PARTIAL = COP * NCOLP;               // floats per block
+    static constexpr int XT = (kWTH + 2) * (kTW + 2) * CST;   // halo tile floats
+    static constexpr int AUX = LowTile<Dt::F32, CU, kWTH>::SIZE > kWTH * kTW * CO
+                                   ? LowTile<Dt::F32, CU, kWTH>::SIZE : kWTH * kTW * CO;
+    static constexpr size_t SMEM = (size_t)(XT + AUX) * 4;
+    static_assert(4 % NFCO == 0, "1, 2 or 4 output fragments");
+    static_assert(CST % 4 == 0 && CIP % 4 == 0, "16-byte aligned channel runs");
+    static_assert((PS - 1) * NFCO * 4 * 64 * 4 <= XT + AUX, "the step-split sums are staged in the tile");
 };
 
 struct WgradArgs {
@@ -212,39 +233,56 @@ struct WgradArgs {
 template <int CS, int CU, int CO>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     using G = WG<CS, CU, CO>;
-    constexpr int TH = kWTH, WP = kTW + 2, NPIX = (TH + 2) * WP, TPX = TH * kTW;
-    constexpr int CST = G::CST, FPW = G::FPW, NFCO = G::NFCO;
-    __shared__ __attribute__((aligned(16))) float xt[NPIX * CST];
-    __shared__ __attribute__((aligned(16))) float dzt[TPX * CO];
-    __shared__ __attribute__((aligned(16))) float lowt[LowTile<Dt::F32, CU, TH>::SIZE];
+    constexpr int TH = kWTH, WP = kTW + 2, TPX = TH * kTW, NSTEP = TPX / 4;
+    constexpr int CST = G::CST, UPW = G::UPW, PS = G::PS;
+    // the low-res rows are needed only while the tile is built, so the
+    // output-gradient tile reuses their space
+    __shared__ __attribute__((aligned(16))) float smem[G::XT + G::AUX];
+    float* const xt = smem;
+    float* const lowt = smem + G::XT;
+    float* const dzt = smem + G::XT;
 
     // the wave index is uniform in the wave: keep it in a scalar register
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int col = lane & 15, g = lane >> 4;
-    // per owned column fragment: LDS offset of this lane's (tap, channel), -1 bias column, -2 padding
-    int boff[FPW];
+    const int n16 = lane & 15, g = lane >> 4;
+    const int f = wave / G::WPF, r = wave - f * G::WPF;
+    const int phase = PS > 1 ? r : 0;
+    // the wave's groups and, per group, the LDS offset of this lane's run of
+    // 4 columns (-1: the run that starts with the bias column, -2: padding)
+    int grp[UPW], boff[UPW];
 #pragma unroll
-    for (int i = 0; i < FPW; ++i) {
-        const int fcol = wave * FPW + i;
-        const int j = fcol * 16 + col;
+    for (int k = 0; k < UPW; ++k) {
+        const int gi = G::BY_GROUP ? r + k * G::WPF : k;
+        grp[k] = gi;
+        const int j = gi * 64 + 4 * n16;
         int o = -2;
-        if (fcol < G::NFCOL) {
-            if (j < G::NCOL) {
-                const int tap = j / G::CIP, ci = j - tap * G::CIP;
-                const int ky = tap / 3, kx = tap - ky * 3;
-                const bool real = ci < CS || ci >= G::CSP;
-                o = real ? (ky * WP + kx) * CST + ci : -2;
-            } else if (j == G::NCOLP - 16) {
-                o = -1;
-            }
+        if (j < G::NCOL) {
+            const int tap = j / G::CIP, ci = j - tap * G::CIP;
+            const int ky = tap / 3, kx = tap - ky * 3;
+            o = (ky * WP + kx) * CST + ci;     // padding channels of the tile hold zeros
+        } else if (j == G::NCOLP - 16) {
+            o = -1;
         }
-        boff[i] = o;
+        boff[k] = o;
     }
-    f32x4 acc[NFCO][FPW];
+    const int co = f * 16 + n16;
+    f32x4 acc[UPW][4];
 #pragma unroll
-    for (int f = 0; f < NFCO; ++f)
+    for (int k = 0; k < UPW; ++k)
 #pragma unroll
-        for (int i = 0; i < FPW; ++i) acc[f][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 4; ++i) acc[k][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    auto load_ops = [&](int s, float& av, f32x4 (&bv)[UPW]) {
+        const int px = 4 * s + g;
+        const int poff = ((px / kTW) * WP + (px % kTW)) * CST;
+        av = (co < CO) ? dzt[px * CO + co] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UPW; ++k) {
+            const int o = boff[k];
+            bv[k] = o >= 0 ? *reinterpret_cast<const f32x4*>(&xt[poff + o])
+                           : (o == -1 ? f32x4{1.f, 0.f, 0.f, 0.f} : f32x4{0.f, 0.f, 0.f, 0.f});
+        }
+    };
 
     const int tiles_x = (a.w + kTW - 1) / kTW, tiles_y = (a.h + TH - 1) / TH;
     const long long total = (long long)a.n * tiles_x * tiles_y;
@@ -255,7 +293,7 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
         const int n = (int)(t / ((long long)tiles_x * tiles_y));
         const int x0 = tx * kTW, y0 = ty * TH;
         __syncthreads();
-        // pixel-major here (the wgrad walk indexes single channels of a pixel)
+        // pixel-major here (the walk reads runs of channels of one pixel)
         load_halo_tile<Dt::F32, (CS % 4 != 0), CS, CU, CST, DT<Dt::F32>::EPB, TH>(xt, lowt, a.in, a.low, n, a.h,
                                                                                 a.w, x0, y0);
         for (int idx = threadIdx.x; idx < TPX * (CO / 4); idx += 256) {
@@ -267,60 +305,113 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
             *reinterpret_cast<f32x4*>(&dzt[px * CO + 4 * c4]) = v;
         }
         __syncthreads();
-        for (int s = 0; s < TPX / 4; ++s) {
-            const int px = 4 * s + g;
-            const int poff = ((px / kTW) * WP + (px % kTW)) * CST;
-            float av[NFCO];
+        // the operands of the next step are read while this step's MFMAs run
+        float av;
+        f32x4 bv[UPW];
+        load_ops(phase, av, bv);
+        for (int s = phase; s < NSTEP; s += PS) {
+            float an = 0.0f;
+            f32x4 bn[UPW];
+            if (s + PS < NSTEP) load_ops(s + PS, an, bn);
 #pragma unroll
-            for (int f = 0; f < NFCO; ++f) {
-                const int co = f * 16 + col;
-                av[f] = (co < CO) ? dzt[px * CO + co] : 0.0f;
+            for (int k = 0; k < UPW; ++k) {
+                if (!G::BY_GROUP || grp[k] < G::NG) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[k][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[k][i], acc[k][i], 0, 0, 0);
+                }
             }
+            av = an;
 #pragma unroll
-            for (int i = 0; i < FPW; ++i) {
-                const int o = boff[i];
-                const float bv = o >= 0 ? xt[poff + o] : (o == -1 ? 1.0f : 0.0f);
-#pragma unroll
-                for (int f = 0; f < NFCO; ++f)
-                    acc[f][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f], bv, acc[f][i], 0, 0, 0);
-            }
+            for (int k = 0; k < UPW; ++k) bv[k] = bn[k];
         }
     }
     float* out = a.partial + (size_t)blockIdx.x * G::PARTIAL;
+    auto store = [&](int k) {
 #pragma unroll
-    for (int f = 0; f < NFCO; ++f)
-#pragma unroll
-        for (int i = 0; i < FPW; ++i) {
-            const int fcol = wave * FPW + i;
-            if (fcol >= G::NFCOL) continue;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                out[(size_t)(f * 16 + 4 * g + e) * G::NCOLP + fcol * 16 + col] = acc[f][i][e];
+                out[(size_t)(f * 16 + 4 * g + e) * G::NCOLP + grp[k] * 64 + 4 * n16 + i] = acc[k][i][e];
+    };
+    if constexpr (PS > 1) {
+        // group by group: the waves of phase > 0 stage their sums, the phase-0
+        // wave of the fragment adds them in phase order and stores
+        f32x4* stage = reinterpret_cast<f32x4*>(smem);
+#pragma unroll
+        for (int k = 0; k < UPW; ++k) {
+            __syncthreads();
+            if (phase > 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) stage[((f * (PS - 1) + phase - 1) * 4 + i) * 64 + lane] = acc[k][i];
+            }
+            __syncthreads();
+            if (phase == 0) {
+                for (int p = 1; p < PS; ++p) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const f32x4 v = stage[((f * (PS - 1) + p - 1) * 4 + i) * 64 + lane];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[k][i][e] += v[e];
+                    }
+                }
+                store(k);
+            }
         }
+    } else {
+#pragma unroll
+        for (int k = 0; k < UPW; ++k)
+            if (grp[k] < G::NG) store(k);
+    }
 }
 
-// Sum the per-block partials in block order into the flat OHWI weights and biases.
-__global__ void k_wgrad_reduce(const float* __restrict__ partial, int grid, int partial_floats, int cs,
-                               int cu, int co, int csp, int cip, int ncolp, float* __restrict__ dw,
-                               float* __restrict__ db, int accumulate) {
-    const int ci_tot = cs + cu;
-    const int nw = co * 9 * ci_tot;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw + co) return;
-    int row, colj;
+// Sum the per-block partials of one channel range of a stage into the flat
+// OHWI weights (channels [c_lo, c_lo + cs + cu) of ci_tot) and, with
+// `bias`, the biases.  Column of part channel pc and tap t: t * cip + pc for
+// pc < cs, t * cip + csp + (pc - cs) above.  Each block takes 16 outputs x 16
+// slices of the blocks' partials; a slice sums its partials in block order
+// and the slice sums are added in slice order.
+constexpr int kReduceOuts = 16, kReduceSlices = 16;
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ partial, int grid,
+                                                      int partial_floats, int co, int ci_tot, int c_lo, int cs,
+                                                      int cu, int csp, int cip, int ncolp, int bias,
+                                                      float* __restrict__ dw, float* __restrict__ db,
+                                                      int accumulate) {
+    __shared__ float part_sum[kReduceSlices][kReduceOuts];
+    const int cp = cs + cu;
+    const int nw = co * 9 * cp;
+    const int nout = nw + (bias ? co : 0);
+    const int oi = threadIdx.x % kReduceOuts, slice = threadIdx.x / kReduceOuts;
+    const int i = blockIdx.x * kReduceOuts + oi;
+    int row = 0, colj = 0;
     if (i < nw) {
-        const int ci = i % ci_tot, tap = (i / ci_tot) % 9, o = i / (9 * ci_tot);
-        const int lc = ci < cs ? ci : csp + (ci - cs);
+        const int pc = i % cp, tap = (i / cp) % 9, o = i / (9 * cp);
         row = o;
-        colj = tap * cip + lc;
-    } else {
+        colj = tap * cip + (pc < cs ? pc : csp + (pc - cs));
+    } else if (i < nout) {
         row = i - nw;
         colj = ncolp - 16;
     }
     float s = 0.0f;
-    for (int b = 0; b < grid; ++b) s += partial[(size_t)b * partial_floats + (size_t)row * ncolp + colj];
-    float* dst = (i < nw) ? dw + i : db + (i - nw);
-    *dst = accumulate ? *dst + s : s;
+    if (i < nout) {
+        const int b0 = grid * slice / kReduceSlices, b1 = grid * (slice + 1) / kReduceSlices;
+        const float* src = partial + (size_t)row * ncolp + colj;
+        for (int b = b0; b < b1; ++b) s += src[(size_t)b * partial_floats];
+    }
+    part_sum[slice][oi] = s;
+    __syncthreads();
+    if (slice != 0 || i >= nout) return;
+    float t = part_sum[0][oi];
+#pragma unroll
+    for (int k = 1; k < kReduceSlices; ++k) t += part_sum[k][oi];
+    float* dst;
+    if (i < nw) {
+        const int pc = i % cp, tap = (i / cp) % 9, o = i / (9 * cp);
+        dst = dw + ((size_t)o * 9 + tap) * ci_tot + c_lo + pc;
+    } else {
+        dst = db + (i - nw);
+    }
+    *dst = accumulate ? *dst + t : t;
 }
 
 #define NSM_BWD_STAGES(X) \
@@ -388,14 +479,79 @@ hipError_t pool_transpose_mask(int c, int ci_total, const float* dskip, const fl
     return hipGetLastError();
 }
 
-int wgrad_grid(int n, int h, int w) {
+// Blocks of a wgrad GEMM: as many as the device holds at once (up to 4 per
+// CU; the small-channel stages are bound by their tile loads and need the
+// blocks in flight), never more than there are tiles.  The partial sums, and
+// so the bits of the result, depend on this count, which is fixed for a
+// given device model.
+template <int CS, int CU, int CO>
+int wgrad_grid_t(int n, int h, int w) {
+    static const int cap = [] {
+        int dev = 0, cus = 256, per = 1;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_wgrad<CS, CU, CO>, 256, 0) != hipSuccess || per < 1)
+            per = 1;
+        return std::min(per, 4) * cus;
+    }();
     const long long tiles = (long long)n * ((w + kTW - 1) / kTW) * ((h + kWTH - 1) / kWTH);
-    return (int)std::min<long long>(kWgradMaxGrid, tiles);
+    return (int)std::min<long long>(cap, tiles);
+}
+
+// A stage whose full tile would hold the LDS to one block per CU runs its
+// skip and upsampled channels as two GEMMs over their own (smaller) tiles.
+template <int CS, int CU, int CO>
+constexpr bool wgrad_split() {
+    return CS > 0 && CU > 0 && WG<CS, CU, CO>::SMEM > 80 * 1024;
+}
+
+template <int CS, int CU, int CO>
+size_t wgrad_partial_floats_t(int n, int h, int w) {
+    if constexpr (wgrad_split<CS, CU, CO>())
+        return (size_t)WG<CS, 0, CO>::PARTIAL * wgrad_grid_t<CS, 0, CO>(n, h, w) +
+               (size_t)WG<0, CU, CO>::PARTIAL * wgrad_grid_t<0, CU, CO>(n, h, w);
+    else
+        return (size_t)WG<CS, CU, CO>::PARTIAL * wgrad_grid_t<CS, CU, CO>(n, h, w);
+}
+
+// One GEMM over channels [c_lo, c_lo + PCS + PCU) of a stage with CI_TOT
+// input channels; `bias` adds the bias column's sums.
+template <int PCS, int PCU, int CO>
+hipError_t wgrad_part(const float* in, const float* low, const float* dz, int n, int h, int w, float* partial,
+                      int ci_tot, int c_lo, bool bias, float* dw, float* db, bool accumulate, hipStream_t s,
+                      const char* name) {
+    using G = WG<PCS, PCU, CO>;
+    const int grid = wgrad_grid_t<PCS, PCU, CO>(n, h, w);
+    WgradArgs a{in, low, dz, partial, n, h, w};
+    {
+        TraceScope ts("wgrad ", name, s);
+        k_wgrad<PCS, PCU, CO><<<grid, 256, 0, s>>>(a);
+    }
+    const int nout = CO * 9 * (PCS + PCU) + (bias ? CO : 0);
+    TraceScope ts2("wgrad_reduce ", name, s);
+    k_wgrad_reduce<<<div_up(nout, kReduceOuts), kReduceOuts * kReduceSlices, 0, s>>>(partial, grid, G::PARTIAL, CO, ci_tot, c_lo, PCS, PCU, G::CSP,
+                                                    G::CIP, G::NCOLP, bias ? 1 : 0, dw, db, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int CS, int CU, int CO>
+hipError_t wgrad_stage(const float* in, const float* low, const float* dz, int n, int h, int w, float* partial,
+                       float* dw, float* db, bool accumulate, hipStream_t s, const char* name) {
+    if constexpr (wgrad_split<CS, CU, CO>()) {
+        const size_t skip_floats = (size_t)WG<CS, 0, CO>::PARTIAL * wgrad_grid_t<CS, 0, CO>(n, h, w);
+        hipError_t e = wgrad_part<CS, 0, CO>(in, nullptr, dz, n, h, w, partial, CS + CU, 0, true, dw, db,
+                                             accumulate, s, name);
+        if (e != hipSuccess) return e;
+        return wgrad_part<0, CU, CO>(nullptr, low, dz, n, h, w, partial + skip_floats, CS + CU, CS, false, dw, db,
+                                     accumulate, s, name);
+    } else {
+        return wgrad_part<CS, CU, CO>(in, low, dz, n, h, w, partial, CS + CU, 0, true, dw, db, accumulate, s, name);
+    }
 }
 
 size_t wgrad_partial_floats(const ConvStage& st, int n, int h, int w) {
 #define NSM_WPF(CS_, CU_, CO_) \
-    if (st.cs == CS_ && st.cu == CU_ && st.co == CO_) return (size_t)WG<CS_, CU_, CO_>::PARTIAL * wgrad_grid(n, h, w);
+    if (st.cs == CS_ && st.cu == CU_ && st.co == CO_) return wgrad_partial_floats_t<CS_, CU_, CO_>(n, h, w);
     NSM_BWD_STAGES(NSM_WPF)
 #undef NSM_WPF
     return 0;
@@ -403,22 +559,10 @@ size_t wgrad_partial_floats(const ConvStage& st, int n, int h, int w) {
 
 hipError_t conv_wgrad(const ConvStage& st, const float* in, const float* low, const float* dz, int n,
                       int h, int w, float* partial, float* dw, float* db, bool accumulate, hipStream_t s) {
-    const int grid = wgrad_grid(n, h, w);
-    WgradArgs a{in, low, dz, partial, n, h, w};
 #define NSM_WCASE(CS_, CU_, CO_)                                                                    \
-    if (st.cs == CS_ && st.cu == CU_ && st.co == CO_) {                                             \
-        using G = WG<CS_, CU_, CO_>;                                                                \
-        {                                                                                           \
-            TraceScope ts("wgrad " #CS_ "+" #CU_ "->" #CO_, "", s);                                 \
-            k_wgrad<CS_, CU_, CO_><<<grid, 256, 0, s>>>(a);                                         \
-        }                                                                                           \
-        const int nout = CO_ * 9 * (CS_ + CU_) + CO_;                                               \
-        TraceScope ts2("wgrad_reduce " #CS_ "+" #CU_ "->" #CO_, "", s);                             \
-        k_wgrad_reduce<<<div_up(nout, 256), 256, 0, s>>>(partial, grid, G::PARTIAL, CS_, CU_, CO_,  \
-                                                         G::CSP, G::CIP, G::NCOLP, dw, db,           \
-                                                         accumulate ? 1 : 0);                       \
-        return hipGetLastError();                                                                   \
-    }
+    if (st.cs == CS_ && st.cu == CU_ && st.co == CO_)                                               \
+        return wgrad_stage<CS_, CU_, CO_>(in, low, dz, n, h, w, partial, dw, db, accumulate, s,     \
+                                          #CS_ "+" #CU_ "->" #CO_);
     NSM_BWD_STAGES(NSM_WCASE)
 #undef NSM_WCASE
     return hipErrorInvalidValue;

@@ -59,6 +59,16 @@ struct nsm_ctx {
     bool has_weights = false;
     bool trainable = false;          // FP32 context with backward kernels for every stage
     int variant[16] = {};            // launch variant per stage (NSM_ARCH_UNET): see conv_forward
+    unsigned weights_gen = 0;        // bumped by every nsm_set_weights
+    // the forward whose activations a training workspace holds (nsm_forward_train
+    // or nsm_backward); any other call that may write a workspace clears it
+    struct {
+        const void* ws = nullptr;
+        const float* feat = nullptr;
+        int n = 0, h = 0, w = 0;
+        unsigned gen = 0;
+        bool valid = false;
+    } saved;
 };
 
 extern "C" {
@@ -298,6 +308,8 @@ nsm_status nsm_set_weights(nsm_ctx* ctx, const float* w, size_t n, void* stream)
             return NSM_E_DEVICE;
         }
     }
+    ctx->weights_gen++;
+    ctx->saved.valid = false;
     char* base = reinterpret_cast<char*>(ctx->dbuf);
     float* flat = reinterpret_cast<float*>(base + ctx->flat_off);
     if (hipMemcpyAsync(flat, w, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return NSM_E_DEVICE;
@@ -530,7 +542,7 @@ TrainLayout plan_training(const nsm_ctx* c, int n, int h, int w) {
 }
 
 hipError_t run_backward(const nsm_ctx* c, const float* feat, const float* dvis, int n, int h, int w,
-                        float* dw, bool acc, float* dfeat, char* ws, const TrainLayout& T,
+                        float* dw, bool acc, float* dfeat, char* ws, const TrainLayout& T, bool recompute,
                         hipStream_t s) {
     const char* base = reinterpret_cast<const char*>(c->dbuf);
     const float* flat = reinterpret_cast<const float*>(base + c->flat_off);
@@ -546,8 +558,9 @@ hipError_t run_backward(const nsm_ctx* c, const float* feat, const float* dvis, 
     hipError_t e;
 #define NSM_TRY(x) \
     if ((e = (x)) != hipSuccess) return e
-    // recompute the forward, keeping every activation (float32)
-    NSM_TRY(run_forward(c, feat, n, h, w, F(T.vis), nullptr, ws, L, F(L.d0act), s));
+    // recompute the forward, keeping every activation (float32), unless the
+    // workspace already holds them
+    if (recompute) NSM_TRY(run_forward(c, feat, n, h, w, F(T.vis), nullptr, ws, L, F(L.d0act), s));
     // sigmoid + 1x1 head
     const size_t npix = (size_t)n * h * w;
     NSM_TRY(head_backward(wd[0], F(T.vis), dvis, F(L.d0act), flat + c->head_w_off, npix, F(T.dzD[0]),
@@ -620,6 +633,7 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
     if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ctx->saved.valid = false;
     debug_sync_begin();
     char* ws = reinterpret_cast<char*>(workspace);
     const hipError_t e = paper ? run_forward_paper(ctx, feat, n, h, w, vis_out, logits_out, ws, L, s)
@@ -640,6 +654,7 @@ nsm_status nsm_autotune(nsm_ctx* ctx, const float* feat, int n, int h, int w, fl
     if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ctx->saved.valid = false;
     char* ws = reinterpret_cast<char*>(workspace);
     // one forward with the current variants leaves every stage's input in the workspace
     if (run_forward(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr, s) != hipSuccess) return NSM_E_LAUNCH;
@@ -700,10 +715,52 @@ nsm_status nsm_get_stage_variants(const nsm_ctx* ctx, int* variants, int max, in
     return NSM_OK;
 }
 
+static nsm_status backward_common(nsm_ctx* ctx, const float* feat, const float* dvis, int n, int h, int w,
+                                  float* dw_out, int accumulate, float* dfeat_out, void* workspace, size_t ws_bytes,
+                                  void* stream, bool saved) {
+    if (!ctx || !feat || !dvis || !dw_out) return NSM_E_INVALID_ARG;
+    nsm_status st = check_net_shape(ctx, n, h, w);
+    if (st != NSM_OK) return st;
+    if (!ctx->trainable) return NSM_E_UNSUPPORTED;
+    if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
+    TrainLayout T = plan_training(ctx, n, h, w);
+    if (!workspace || ws_bytes < T.total) return NSM_E_WORKSPACE;
+    if (saved) {
+        const auto& sv = ctx->saved;
+        if (!sv.valid || sv.ws != workspace || sv.feat != feat || sv.n != n || sv.h != h || sv.w != w ||
+            sv.gen != ctx->weights_gen)
+            return NSM_E_INVALID_ARG;
+    }
+    if (!device_ok()) return NSM_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ctx->saved.valid = false;
+    debug_sync_begin();
+    if (run_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate != 0, dfeat_out,
+                     reinterpret_cast<char*>(workspace), T, !saved, s) != hipSuccess)
+        return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
+    // the workspace holds this forward's activations (the adjoint only reads them)
+    ctx->saved = {workspace, feat, n, h, w, ctx->weights_gen, true};
+    return NSM_OK;
+}
+
 nsm_status nsm_backward(nsm_ctx* ctx, const float* feat, const float* dvis, int n, int h, int w,
                         float* dw_out, int accumulate, float* dfeat_out, void* workspace,
                         size_t ws_bytes, void* stream) {
-    if (!ctx || !feat || !dvis || !dw_out) return NSM_E_INVALID_ARG;
+    return backward_common(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, workspace, ws_bytes, stream,
+                           false);
+}
+
+nsm_status nsm_backward_saved(nsm_ctx* ctx, const float* feat, const float* dvis, int n, int h, int w,
+                              float* dw_out, int accumulate, float* dfeat_out, void* workspace,
+                              size_t ws_bytes, void* stream) {
+    return backward_common(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, workspace, ws_bytes, stream,
+                           true);
+}
+
+nsm_status nsm_forward_train(nsm_ctx* ctx, const float* feat, int n, int h, int w, float* vis_out,
+                             void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || !feat) return NSM_E_INVALID_ARG;
     nsm_status st = check_net_shape(ctx, n, h, w);
     if (st != NSM_OK) return st;
     if (!ctx->trainable) return NSM_E_UNSUPPORTED;
@@ -712,11 +769,17 @@ nsm_status nsm_backward(nsm_ctx* ctx, const float* feat, const float* dvis, int 
     if (!workspace || ws_bytes < T.total) return NSM_E_WORKSPACE;
     if (!device_ok()) return NSM_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ctx->saved.valid = false;
     debug_sync_begin();
-    if (run_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate != 0, dfeat_out,
-                     reinterpret_cast<char*>(workspace), T, s) != hipSuccess)
+    char* ws = reinterpret_cast<char*>(workspace);
+    float* vis = reinterpret_cast<float*>(ws + T.vis);
+    if (run_forward(ctx, feat, n, h, w, vis, nullptr, ws, T.f, reinterpret_cast<float*>(ws + T.f.d0act), s) !=
+        hipSuccess)
+        return NSM_E_LAUNCH;
+    if (vis_out && hipMemcpyAsync(vis_out, vis, (size_t)n * h * w * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return NSM_E_LAUNCH;
     if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
+    ctx->saved = {workspace, feat, n, h, w, ctx->weights_gen, true};
     return NSM_OK;
 }
 

@@ -368,3 +368,44 @@ def test_autograd_function_and_training_step():
         losses.append(float(loss))
     print(f"[train] loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_saved_forward_backward_same_bits():
+    """nsm_forward_train + nsm_backward_saved: the visibility is nsm_forward's
+    and the gradients are nsm_backward's, bit for bit; the saved forward is
+    refused after nsm_set_weights, nsm_forward, or for other features."""
+    import paper_2301_05262_amd as nsm
+    desc, (n, h, w) = S.U3_SOFT, (2, 64, 96)
+    flat = S.he_weights(desc, 17, bias_scale=0.1)
+    m = _net(desc, flat)
+    feat = torch.from_numpy(_rand((n, h, w, desc.c_in), 18)).cuda()
+    dvis = torch.from_numpy(_rand((n, h, w), 19)).cuda()
+    vis_inf = m.forward(feat).clone()
+    vis_tr = m.forward_train(feat)
+    dw_s, df_s = m.backward(feat, dvis, saved=True)
+    dw_s, df_s = dw_s.clone(), df_s.clone()
+    dw_s2, _ = m.backward(feat, dvis, saved=True)        # the adjoint leaves the activations intact
+    dw_s2 = dw_s2.clone()
+    dw_r, df_r = m.backward(feat, dvis)
+    torch.cuda.synchronize()
+    assert torch.equal(vis_inf, vis_tr)
+    assert torch.equal(dw_s, dw_r) and torch.equal(df_s, df_r) and torch.equal(dw_s2, dw_r)
+    # after the recomputing backward the workspace holds this forward again
+    dw_s3, _ = m.backward(feat, dvis, saved=True)
+    torch.cuda.synchronize()
+    assert torch.equal(dw_s3, dw_r)
+
+    def refused():
+        with pytest.raises(nsm.NsmError) as ei:
+            m.backward(feat, dvis, saved=True)
+        assert ei.value.status == 1
+
+    m.forward(feat)
+    refused()
+    m.forward_train(feat)
+    m.set_weights(torch.from_numpy(flat))
+    refused()
+    m.forward_train(feat)
+    other = feat.clone()
+    with pytest.raises(nsm.NsmError):
+        m.backward(other, dvis, saved=True)
