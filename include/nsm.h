@@ -171,7 +171,8 @@ const char *nsm_status_str(int status);
  *   feat_out    [h][w][C] float32, C = 6 (HARD6), 8 (SOFT8) or 4 (PAPER4).
  *   mask_out    [h][w] uint8 hard depth-test result (1 = shadowed), or NULL.
  * The rasteriser and the gather are deterministic: repeated calls give
- * identical bits.  Triangles with a vertex at w_clip <= 1e-6 or beyond the
+ * identical bits.  With SOFT8 the workspace also holds the linear-depth copy
+ * of the light-view map that the z_blk search reads.  Triangles with a vertex at w_clip <= 1e-6 or beyond the
  * guard band [-8, 9] x the target size are skipped. */
 nsm_status nsm_features_workspace_bytes(int n_tris, int h, int w, int sm_size, size_t *bytes);
 nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n_tris,

@@ -80,8 +80,12 @@ struct GatherParams {
     float tau;                // (2 tanl) / S, float32
     double rw, rh;            // 1 / w and 1 / h, float64, rounded to nearest
 };
+// Bytes of the linear-depth copy of an S x S shadow map (SOFT8's blocker search).
+size_t linear_map_bytes(int sm_size);
+// `lsm` (linear_map_bytes) receives the linear-depth copy of the map first
+// when fs is SOFT8; unused otherwise.
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
-                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
+                  const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s);
 
 // ------------------------------------------------------ temporal stability

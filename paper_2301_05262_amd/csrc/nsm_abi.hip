@@ -95,7 +95,8 @@ nsm_status nsm_features_workspace_bytes(int n_tris, int h, int w, int sm_size, s
     if (n_tris > kMaxTris) return NSM_E_SHAPE;
     if (h < 1 || w < 1 || h > kMaxImage || w > kMaxImage || sm_size < 1 || sm_size > kMaxImage)
         return NSM_E_SHAPE;
-    *bytes = align256(raster_workspace_bytes(n_tris)) + align256((size_t)h * (size_t)w * 8);
+    *bytes = align256(raster_workspace_bytes(n_tris)) + align256((size_t)h * (size_t)w * 8) +
+             linear_map_bytes(sm_size);
     return NSM_OK;
 }
 
@@ -116,6 +117,8 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     debug_sync_begin();
     char* ws = reinterpret_cast<char*>(workspace);
     uint64_t* gbuf_ws = reinterpret_cast<uint64_t*>(ws + align256(raster_workspace_bytes(n_tris)));
+    float* lsm_ws = reinterpret_cast<float*>(ws + align256(raster_workspace_bytes(n_tris)) +
+                                             align256((size_t)h * (size_t)w * 8));
 
     Mat4 ml, mc;
     std::memcpy(ml.m, fp->m_light, sizeof(ml.m));
@@ -151,7 +154,7 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     gp.tanx = fp->cam_tan_half_x;
     gp.tany = fp->cam_tan_half_y;
     gp.fc = fp->cam_far;
-    if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, w, h, (int)fs, feat_out,
+    if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, lsm_ws, w, h, (int)fs, feat_out,
                mask_out, s) != hipSuccess)
         return NSM_E_LAUNCH;
     if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;

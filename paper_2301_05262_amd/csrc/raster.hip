@@ -488,6 +488,30 @@ __device__ __forceinline__ float lin_depth(float q, float nl, float fl) {
     return num / den;
 }
 
+// Linear light-view depth of every shadow-map texel, +inf where the map is
+// empty: the SOFT8 blocker search reads 49 texels per pixel, and this turns
+// their 49 divisions into one per texel.  lin_depth is a pure function of the
+// texel, so the search sees the same values either way.  Four texels per
+// thread (16-byte accesses); the tail runs one per thread.
+__global__ void __launch_bounds__(256) k_linear_map(const uint32_t* __restrict__ sm, size_t n, float nl, float fl,
+                                                    float* __restrict__ lsm) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n4 = n / 4;
+    if (i < n4) {
+        const uint4 b = reinterpret_cast<const uint4*>(sm)[i];
+        float4 o;
+        o.x = b.x == kEmptyDepth ? __uint_as_float(kEmptyDepth) : lin_depth(__uint_as_float(b.x), nl, fl);
+        o.y = b.y == kEmptyDepth ? __uint_as_float(kEmptyDepth) : lin_depth(__uint_as_float(b.y), nl, fl);
+        o.z = b.z == kEmptyDepth ? __uint_as_float(kEmptyDepth) : lin_depth(__uint_as_float(b.z), nl, fl);
+        o.w = b.w == kEmptyDepth ? __uint_as_float(kEmptyDepth) : lin_depth(__uint_as_float(b.w), nl, fl);
+        reinterpret_cast<float4*>(lsm)[i] = o;
+    } else if (i < n4 + (n & 3)) {
+        const size_t t = 4 * n4 + (i - n4);
+        const uint32_t b = sm[t];
+        lsm[t] = b == kEmptyDepth ? __uint_as_float(kEmptyDepth) : lin_depth(__uint_as_float(b), nl, fl);
+    }
+}
+
 // FS: 0 = HARD6, 1 = SOFT8, 2 = PAPER4
 //
 // Each thread carries kGatherPx pixels of one row (stride 256) through the
@@ -503,8 +527,9 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                                                 const float* __restrict__ normals, int n_tris,
                                                 GatherParams P,
                                                 const unsigned long long* __restrict__ gbuf,
-                                                const uint32_t* __restrict__ sm, int w, int h,
-                                                float* __restrict__ feat, uint8_t* __restrict__ mask) {
+                                                const uint32_t* __restrict__ sm, const float* __restrict__ lsm,
+                                                int w, int h, float* __restrict__ feat,
+                                                uint8_t* __restrict__ mask) {
     constexpr bool SOFT = FS == 1;
     constexpr int C = FS == 1 ? 8 : (FS == 2 ? 4 : 6);
     constexpr int PX = kGatherPx;
@@ -648,16 +673,27 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                     const float thr = zf[k] - beta;
                     float sum = 0.0f;
                     int cnt = 0;
+                    // all 49 loads issued together: indices clamped into the map,
+                    // out-of-map taps masked (the same taps, summed in the same order)
+                    float qv[49];
+#pragma unroll
                     for (int dj = -3; dj <= 3; ++dj) {
-                        const int jj = tj[k] + dj;
-                        if (jj < 0 || jj >= P.S) continue;
+                        const int jj = min(max(tj[k] + dj, 0), P.S - 1);
+#pragma unroll
                         for (int di = -3; di <= 3; ++di) {
-                            const int ii = ti[k] + di;
-                            if (ii < 0 || ii >= P.S) continue;
-                            const uint32_t b = sm[(size_t)jj * (size_t)P.S + (size_t)ii];
-                            if (b == kEmptyDepth) continue;
-                            const float q = lin_depth(__uint_as_float(b), P.nl, P.fl);
-                            if (q < thr) { sum = sum + q; ++cnt; }
+                            const int ii = min(max(ti[k] + di, 0), P.S - 1);
+                            qv[(dj + 3) * 7 + di + 3] = lsm[(size_t)jj * (size_t)P.S + (size_t)ii];
+                        }
+                    }
+#pragma unroll
+                    for (int dj = -3; dj <= 3; ++dj) {
+                        const bool okj = tj[k] + dj >= 0 && tj[k] + dj < P.S;
+#pragma unroll
+                        for (int di = -3; di <= 3; ++di) {
+                            const bool ok = okj && ti[k] + di >= 0 && ti[k] + di < P.S;
+                            // +inf where the map is empty: never below the threshold
+                            const float q = qv[(dj + 3) * 7 + di + 3];
+                            if (ok && q < thr) { sum = sum + q; ++cnt; }
                         }
                     }
                     if (cnt > 0) zb = sum / (float)cnt;
@@ -727,8 +763,10 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     return hipGetLastError();
 }
 
+size_t linear_map_bytes(int sm_size) { return align256((size_t)sm_size * (size_t)sm_size * 4); }
+
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& params,
-                  const uint64_t* gbuf, const uint32_t* sm, int w, int h, int fs, float* feat,
+                  const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, float* feat,
                   uint8_t* mask, hipStream_t s) {
     GatherParams p = params;
     p.tau = (2.0f * p.tanl) / (float)p.S;
@@ -736,13 +774,19 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
     p.rh = 1.0 / (double)h;
     dim3 grid((w + 256 * kGatherPx - 1) / (256 * kGatherPx), h);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
+    if (fs == 1) {
+        const size_t n = (size_t)p.S * (size_t)p.S;
+        const size_t threads = n / 4 + (n & 3);
+        TraceScope ts("linear_map", "", s);
+        k_linear_map<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sm, n, p.nl, p.fl, lsm);
+    }
     TraceScope ts("gather", fs == 1 ? " soft8" : (fs == 2 ? " paper4" : " hard6"), s);
     if (fs == 1)
-        k_gather<1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
+        k_gather<1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
     else if (fs == 2)
-        k_gather<2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
+        k_gather<2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
     else
-        k_gather<0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, w, h, feat, mask);
+        k_gather<0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
     return hipGetLastError();
 }
 
