@@ -96,15 +96,20 @@ __global__ void k_pack_up(const float* __restrict__ w, void* __restrict__ out) {
     const int lane = (int)((idx / EPB) % 64);
     const int co_l = lane & 15, g = lane >> 4;
     double v = 0.0;
-    if (idx < G::SKIP_ELEMS) {
-        const int q = (int)((idx / (EPB * 64)) % G::NKG_S);
-        const int f = (int)(idx / ((size_t)EPB * 64 * G::NKG_S));
-        const int co = f * 16 + co_l, b = 4 * q + g;
-        if (b < G::NB_S && co < CO) {
-            const int tap = b / G::BPT_S, cb = b % G::BPT_S;
-            v = w[((size_t)co * 9 + tap) * CIN + cb * EPB + e];
+    bool skip_part = false;
+    if constexpr (CS > 0) {       // stages of up() alone have no skip part
+        if (idx < G::SKIP_ELEMS) {
+            skip_part = true;
+            const int q = (int)((idx / (EPB * 64)) % G::NKG_S);
+            const int f = (int)(idx / ((size_t)EPB * 64 * G::NKG_S));
+            const int co = f * 16 + co_l, b = 4 * q + g;
+            if (b < G::NB_S && co < CO) {
+                const int tap = b / G::BPT_S, cb = b % G::BPT_S;
+                v = w[((size_t)co * 9 + tap) * CIN + cb * EPB + e];
+            }
         }
-    } else {
+    }
+    if (!skip_part) {
         const size_t r = idx - G::SKIP_ELEMS;
         const int q = (int)((r / (EPB * 64)) % G::NKG_U);
         const int f = (int)((r / ((size_t)EPB * 64 * G::NKG_U)) % G::NF);

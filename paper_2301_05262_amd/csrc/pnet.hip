@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "conv_kernels.h"
+#include "conv_up.h"
 
 namespace nsm {
 namespace {
@@ -48,8 +49,20 @@ __device__ __forceinline__ f32x4 mfma_1x1(const uint2& wa, const f32x4& act, f32
     }
 }
 
+// LDS elements of one stage tile: the halo tile's block-major planes, then
+// the low-resolution rows (16-byte aligned).
+template <Dt D, int CS, int CU, bool SUM, int C1, int TH>
+struct PTile {
+    using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
+    static constexpr int PS = plane_stride<D>((TH + 2) * (kTW + 2));
+    static constexpr int LOW_OFF = (G::BPT * PS + 7) / 8 * 8;
+    static constexpr int ELEMS = LOW_OFF + LowTile<D, CU, TH>::SIZE;
+};
+
+// One TH x 32 output tile at (x0, y0) of image n: the whole stage for it.
 template <Dt D, bool IN_F32, int CS, int CU, bool SUM, int C1, int C2, PMode MODE, int TH, bool S2D>
-__global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
+__device__ __forceinline__ void pconv_tile(const PConvArgs& a, int x0, int y0, int n, typename DT<D>::T* tile,
+                                           typename DT<D>::T* lowt) {
     using T = typename DT<D>::T;
     using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
     constexpr int EPB = G::EPB, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
@@ -61,14 +74,7 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
     static_assert(!POOL || RPW == 2, "pooling needs row pairs per wave");
     static_assert(C1 % 16 == 0, "the 1x1 reads whole 16-channel fragments");
 
-    __shared__ __attribute__((aligned(16))) T tile[BPT * PS];
-    __shared__ __attribute__((aligned(16))) T lowt[LowTile<D, CU, TH>::SIZE];
-
     const int h = a.h, w = a.w;
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
-    const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
-
     load_halo_tile<D, IN_F32, CS, CU, EPB, PS, TH, SUM, S2D>(tile, lowt, a.in, a.low, n, h, w, x0, y0);
 
     // the wave index is uniform in the wave: keep it in a scalar register
@@ -254,6 +260,207 @@ __global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
                     }
                 }
             }
+        }
+    }
+}
+
+template <Dt D, bool IN_F32, int CS, int CU, bool SUM, int C1, int C2, PMode MODE, int TH, bool S2D>
+__global__ void __launch_bounds__(kThreads) k_pconv(PConvArgs a) {
+    using T = typename DT<D>::T;
+    using PT = PTile<D, CS, CU, SUM, C1, TH>;
+    __shared__ __attribute__((aligned(16))) T smem[PT::ELEMS];
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int lt = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int x0 = (lt % gx) * kTW, y0 = ((lt / gx) % gy) * TH, n = lt / (gx * gy);
+    pconv_tile<D, IN_F32, CS, CU, SUM, C1, C2, MODE, TH, S2D>(a, x0, y0, n, smem, smem + PT::LOW_OFF);
+}
+
+// The full-resolution stage (input up(y_1) alone, 3x3 CU -> C1, 1x1 C1 -> C2,
+// output 1x1 + sigmoid) with the bilinear x2 upsampling folded into four
+// phase kernels over the low-resolution tile, as in the U-Net decoders
+// (conv_up.h: same packing, same tile).  One launch: blocks [0, nb) take
+// the border tiles (TH_G rows, the stage's general form, where the zero
+// padding of up() applies), the rest the interior TH x 32 tiles.
+template <Dt D, int CU, int C1, int TH, int TH_G>
+struct PUp0 {
+    using T = typename DT<D>::T;
+    using G = UpGeo<D, 0, CU, C1>;
+    using UT = UpTile<D, 0, CU, TH>;
+    using PT = PTile<D, 0, CU, false, C1, TH_G>;
+    static constexpr int ELEMS = UT::LOW > PT::ELEMS ? UT::LOW : PT::ELEMS;
+};
+
+template <Dt D, int CU, int C1, int C2, int TH, int TH_G>
+__global__ void __launch_bounds__(kThreads) k_pconv_up0(PConvArgs a, const void* __restrict__ wup) {
+    using T = typename DT<D>::T;
+    using P = PUp0<D, CU, C1, TH, TH_G>;
+    using G = typename P::G;
+    using UT = typename P::UT;
+    using PT = typename P::PT;
+    constexpr int EPB = G::EPB, NF = G::NF, LPS = UT::LPS, RW = TH / 4;
+    constexpr int NF2 = (C2 + 15) / 16;
+    static_assert(TH % 8 == 0 && TH % TH_G == 0, "each wave needs rows of one parity in one half of the tile");
+    __shared__ __attribute__((aligned(16))) T smem[P::ELEMS];
+    const int h = a.h, w = a.w, hl = h >> 1, wl = w >> 1;
+    const int nb = border_tiles_per_image(TH, TH_G, h, w) * a.n;
+    const int b = blockIdx.x;
+    if (b < nb) {
+        int bx, by, bn;
+        border_tile(b, TH, TH_G, h, w, &bx, &by, &bn);
+        pconv_tile<D, false, 0, CU, false, C1, C2, PMode::Head, TH_G, false>(a, bx, by, bn, smem,
+                                                                              smem + PT::LOW_OFF);
+        return;
+    }
+    const int gx = (w + kTW - 1) / kTW - 2, gy = (h + TH - 1) / TH - 2;
+    const int lt = xcd_remap(b - nb, gx * gy * a.n);
+    const int x0 = (lt % gx + 1) * kTW, y0 = ((lt / gx) % gy + 1) * TH, n = lt / (gx * gy);
+    T* lowt = smem;
+    // low-resolution rows y0/2-1 .. y0/2+TH/2 and columns x0/2-1 .. x0/2+16 (in the image)
+    {
+        using S = typename ST<D>::S;
+        constexpr int KL = UT::LC * G::BPT_U, BB = blk_bytes<D>();
+        const S* lbase = reinterpret_cast<const S*>(a.low) + (((size_t)n * hl + (y0 >> 1) - 1) * wl + (x0 >> 1) - 1) * CU;
+        const __amdgpu_buffer_rsrc_t lr = buf_rsrc(lbase);
+        const int lrow = wl * CU * (int)sizeof(S);
+        copy_rows1<UT::LR, KL>(
+            [&](int r, int k) -> u32x4 {
+                const int cb = k / UT::LC, c = k - cb * UT::LC;
+                return load_blk<D>(lr, r * lrow + (c * G::BPT_U + cb) * BB, 0);
+            },
+            [&](int r, int k, const u32x4& v) {
+                const int cb = k / UT::LC, c = k - cb * UT::LC;
+                *reinterpret_cast<u32x4*>(&lowt[cb * LPS + (r * UT::LC + c) * EPB]) = v;
+            },
+            threadIdx.x);
+    }
+    __syncthreads();
+
+    // waves: row parity py = wave & 1, rows RW * half .. of that parity; each
+    // row is two 16-pixel fragments, the even and the odd columns
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int j = lane & 15, g = lane >> 4;
+    const int py = wave & 1, half = wave >> 1, rb = RW * half;
+    f32x4 acc[RW][2][NF];
+#pragma unroll
+    for (int m = 0; m < RW; ++m)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[m][p][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __amdgpu_buffer_rsrc_t wr = buf_rsrc(wup);
+    const int wl16 = lane * 16;
+    const int wph = py * 2 * NF * G::NKG_U * 1024;        // this wave's row phase
+#pragma unroll
+    for (int q = 0; q < G::NKG_U; ++q) {
+        u32x4 w0[NF], w1[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            w0[f] = buf_load16(wr, wl16, wph + (f * G::NKG_U + q) * 1024);
+            w1[f] = buf_load16(wr, wl16, wph + ((NF + f) * G::NKG_U + q) * 1024);
+        }
+        int bk = 4 * q + g;
+        if (bk >= G::NB_U) bk = G::NB_U - 1;
+        const int t = bk / G::BPT_U, cb = bk - t * G::BPT_U;
+        const int ty = t / 3, tx = t - ty * 3;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int r = rb + m + ty;
+            const u32x4 xb = *reinterpret_cast<const u32x4*>(&lowt[cb * LPS + (r * UT::LC + j + tx) * EPB]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                acc[m][0][f] = mfma_kgroup<D>(w0[f], xb, acc[m][0][f]);
+                acc[m][1][f] = mfma_kgroup<D>(w1[f], xb, acc[m][1][f]);
+            }
+        }
+    }
+    // 3x3 bias + ReLU, then the 1x1 on the accumulators, bias + ReLU
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        float bb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bb[e] = a.b1[f * 16 + 4 * g + e];
+#pragma unroll
+        for (int m = 0; m < RW; ++m)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[m][p][f][e] = fmaxf(acc[m][p][f][e] + bb[e], 0.0f);
+    }
+    f32x4 acc2[RW][2][NF2];
+#pragma unroll
+    for (int m = 0; m < RW; ++m)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int f2 = 0; f2 < NF2; ++f2) acc2[m][p][f2] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int f2 = 0; f2 < NF2; ++f2) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if constexpr (D == Dt::F32) {
+                const f32x4 w4 = reinterpret_cast<const f32x4*>(a.w1pk)[(f2 * NF + f) * 64 + lane];
+#pragma unroll
+                for (int m = 0; m < RW; ++m)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc2[m][p][f2] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(w4[e], acc[m][p][f][e], acc2[m][p][f2], 0, 0, 0);
+            } else {
+                const uint2 w4 = reinterpret_cast<const uint2*>(a.w1pk)[(f2 * NF + f) * 64 + lane];
+#pragma unroll
+                for (int m = 0; m < RW; ++m)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) acc2[m][p][f2] = mfma_1x1<D>(w4, acc[m][p][f], acc2[m][p][f2]);
+            }
+        }
+    }
+    float hw[NF2][4];
+#pragma unroll
+    for (int f2 = 0; f2 < NF2; ++f2) {
+        float bb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int co = f2 * 16 + 4 * g + e;
+            bb[e] = co < C2 ? a.b2[co] : 0.0f;
+            hw[f2][e] = co < C2 ? a.head_w[co] : 0.0f;
+        }
+#pragma unroll
+        for (int m = 0; m < RW; ++m)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc2[m][p][f2][e] = fmaxf(acc2[m][p][f2][e] + bb[e], 0.0f);
+    }
+    // output 1x1 + sigmoid: logit of pixel (row m, column 2j + p), complete in
+    // every lane group after the cross-group sum; lane group g writes rows
+    // m with m % 4 == g, two adjacent pixels per 8-byte store
+    const float hb = a.head_w[C2];
+    float s[RW][2];
+#pragma unroll
+    for (int m = 0; m < RW; ++m)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            float v = 0.0f;
+#pragma unroll
+            for (int f2 = 0; f2 < NF2; ++f2)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v += hw[f2][e] * acc2[m][p][f2][e];
+            s[m][p] = sum_rows4(v) + hb;
+        }
+#pragma unroll
+    for (int m0 = 0; m0 < RW; m0 += 4) {
+        if (m0 + g < RW) {
+            float l0 = s[m0][0], l1 = s[m0][1];
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                if (m0 + k < RW && g == k) { l0 = s[m0 + k][0]; l1 = s[m0 + k][1]; }
+            const int y = y0 + py + 2 * (rb + m0 + g), x = x0 + 2 * j;
+            const size_t pi = ((size_t)n * h + y) * w + x;
+            *reinterpret_cast<float2*>(a.vis + pi) =
+                make_float2(1.0f / (1.0f + __expf(-l0)), 1.0f / (1.0f + __expf(-l1)));
+            if (a.logits) *reinterpret_cast<float2*>(a.logits + pi) = make_float2(l0, l1);
         }
     }
 }
@@ -485,6 +692,10 @@ template <Dt D> constexpr const char* pdt_suffix() {
      st.mode == PMode::MODE_ && st.in_f32 == F32_ && st.s2d == S2D_)
 
 template <Dt D>
+bool ppack(const PStage& st, const float* w3, const float* w1, void* out, hipStream_t s, size_t* bytes,
+           size_t* w1_off = nullptr, size_t* up_off = nullptr);
+
+template <Dt D>
 hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* found) {
     // the 256-channel bottleneck runs in the channel-split form (same packed weights)
     if (st.cs == 128 && st.cu == 0 && !st.sum && st.c1 == 256 && st.c2 == 128 && st.mode == PMode::Store &&
@@ -505,6 +716,23 @@ hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* fo
         TraceScope ts("pconv 128+128->128->64 Store split", pdt_suffix<D>(), s);
         k_pconv_cs<D, 128, 128, true, 128, 64, 2><<<grid, kThreads, 0, s>>>(a);
         return hipGetLastError();
+    }
+    // the full-resolution stage of up(y_1): phase form where the image has
+    // interior tiles (16 rows), border tiles in its general form (8 rows)
+    if (st.cs == 0 && st.cu == 16 && !st.sum && st.c1 == 16 && st.c2 == 16 && st.mode == PMode::Head &&
+        !st.in_f32 && !st.s2d) {
+        constexpr int THU = 16, THG = 8;
+        const int gxt = (a.w + kTW - 1) / kTW, gyt = (a.h + THU - 1) / THU;
+        if (gxt >= 3 && gyt >= 3) {
+            *found = true;
+            size_t up_off = 0;
+            ppack<D>(st, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &up_off);
+            const void* wup = reinterpret_cast<const char*>(a.wpk) + up_off;
+            const int blocks = border_tiles_per_image(THU, THG, a.h, a.w) * a.n + (gxt - 2) * (gyt - 2) * a.n;
+            TraceScope ts("pconv 0+16->16->16 Head phase", pdt_suffix<D>(), s);
+            k_pconv_up0<D, 16, 16, 16, THU, THG><<<blocks, kThreads, 0, s>>>(a, wup);
+            return hipGetLastError();
+        }
     }
 #define NSM_PCASE(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_)                               \
     if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)) {                                \
@@ -527,19 +755,31 @@ hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* fo
     return hipErrorInvalidValue;
 }
 
+// Packed weights of a stage: the 3x3 pack, the 1x1 pack (256-byte aligned)
+// and, for the full-resolution stage of up(y_1) alone, the phase-form pack
+// of its 3x3 (conv_up.h, 256-byte aligned).
 template <Dt D>
-bool ppack(const PStage& st, const float* w3, const float* w1, void* out, hipStream_t s, size_t* bytes) {
+bool ppack(const PStage& st, const float* w3, const float* w1, void* out, hipStream_t s, size_t* bytes,
+           size_t* w1_off, size_t* up_off) {
 #define NSM_PPACK(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, TH_, S2D_)                               \
     if (NSM_PMATCH(CS_, CU_, SUM_, C1_, C2_, MODE_, F32_, S2D_)) {                                      \
         constexpr size_t b3 = packed_bytes<D, CS_, (SUM_ ? 0 : CU_), C1_>();                      \
         constexpr size_t b1 = (size_t)((C2_ + 15) / 16) * (C1_ / 16) * 64 * 4 * sizeof(typename DT<D>::T); \
-        if (bytes) *bytes = ((b3 + 255) & ~(size_t)255) + b1;                                     \
+        constexpr bool UP0 = CS_ == 0 && PMode::MODE_ == PMode::Head;                            \
+        constexpr size_t o1 = (b3 + 255) & ~(size_t)255, ou = (o1 + b1 + 255) & ~(size_t)255;    \
+        if (bytes) *bytes = UP0 ? ou + UpGeo<D, 0, (UP0 ? CU_ : 16), C1_>::BYTES : o1 + b1;      \
+        if (w1_off) *w1_off = o1;                                                                 \
+        if (up_off) *up_off = UP0 ? ou : 0;                                                       \
         if (out) {                                                                                \
             constexpr int n3 = (int)(b3 / 16 * DT<D>::EPB);                                       \
             k_pack<D, CS_, (SUM_ ? 0 : CU_), C1_><<<(n3 + 255) / 256, 256, 0, s>>>(w3, out);      \
             constexpr int n1 = (int)(b1 / sizeof(typename DT<D>::T));                             \
-            k_pack1x1<D, C1_, C2_><<<(n1 + 255) / 256, 256, 0, s>>>(                              \
-                w1, reinterpret_cast<char*>(out) + ((b3 + 255) & ~(size_t)255));                  \
+            k_pack1x1<D, C1_, C2_><<<(n1 + 255) / 256, 256, 0, s>>>(w1, reinterpret_cast<char*>(out) + o1); \
+            if constexpr (UP0) {                                                                  \
+                using GU = UpGeo<D, 0, CU_, C1_>;                                                 \
+                constexpr int nu = (int)(4 * GU::PHASE_ELEMS);                                    \
+                k_pack_up<D, 0, CU_, C1_><<<(nu + 255) / 256, 256, 0, s>>>(w3, reinterpret_cast<char*>(out) + ou); \
+            }                                                                                     \
         }                                                                                         \
         return true;                                                                              \
     }
@@ -582,10 +822,14 @@ hipError_t pconv_pack(const PStage& st, Dt dt, const float* w3, const float* w1,
 }
 
 size_t pconv_w1_offset(const PStage& st, Dt dt) {
-    // the 1x1 pack follows the 256-byte aligned 3x3 pack
-    const int NF2 = (st.c2 + 15) / 16, NF1 = st.c1 / 16;
-    const size_t b1 = (size_t)NF2 * NF1 * 64 * 4 * (dt == Dt::F32 ? 4 : 2);
-    return pconv_packed_bytes(st, dt) - b1;
+    size_t o1 = 0;
+    switch (dt) {
+        case Dt::F32: ppack<Dt::F32>(st, nullptr, nullptr, nullptr, nullptr, nullptr, &o1); break;
+        case Dt::BF16: ppack<Dt::BF16>(st, nullptr, nullptr, nullptr, nullptr, nullptr, &o1); break;
+        case Dt::F16: ppack<Dt::F16>(st, nullptr, nullptr, nullptr, nullptr, nullptr, &o1); break;
+        default: break;
+    }
+    return o1;
 }
 
 hipError_t d2s_forward(const float* y4, int n, int h, int w, float* vis, float* logits, hipStream_t s) {
