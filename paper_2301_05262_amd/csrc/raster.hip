@@ -521,6 +521,7 @@ __global__ void __launch_bounds__(256) k_linear_map(const uint32_t* __restrict__
 // frame, one pixel per thread with more waves in flight beats four per
 // thread: the gather is bound by its vector ALU work as much as by latency.
 constexpr int kGatherPx = 1;
+constexpr int kWinCap = 1024;     // texels of a wave's staged window box (4 KB of LDS)
 
 template <int FS>
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
@@ -533,14 +534,16 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
     constexpr bool SOFT = FS == 1;
     constexpr int C = FS == 1 ? 8 : (FS == 2 ? 4 : 6);
     constexpr int PX = kGatherPx;
-    const int j = blockIdx.y;
-    const int ib = blockIdx.x * (256 * PX) + threadIdx.x;
+    // 16 x 16 pixels per block, 8 x 8 per wave: compact shadow-map footprints
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int j = blockIdx.y * 16 + (wv >> 1) * 8 + (ln >> 3);
+    const int ib = blockIdx.x * 16 + (wv & 1) * 8 + (ln & 7);
     // stage 1: camera keys
     unsigned long long key[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const int i = ib + 256 * k;
-        key[k] = (i < w) ? gbuf[(size_t)j * (size_t)w + (size_t)i] : kEmptyKey;
+        key[k] = (i < w && j < h) ? gbuf[(size_t)j * (size_t)w + (size_t)i] : kEmptyKey;
     }
     // stage 2: the keys' triangles (vertex 0 and the face normal)
     float V0[PX][3], N[PX][3];
@@ -611,11 +614,44 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
     uint32_t tex[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k) tex[k] = sm[(size_t)tj[k] * (size_t)P.S + (size_t)ti[k]];
+    // stage 4b (SOFT8): when the 7x7 windows of the wave's 8 x 8 pixels fit a
+    // small box of the map, the wave stages that box in LDS (one coalesced
+    // row per load) and the blocker search reads it from there
+    bool win_lds = false;
+    int wx0 = 0, wy0 = 0, wrw = 1;
+    __shared__ float win[4][kWinCap];
+    if constexpr (SOFT) {
+        static_assert(PX == 1, "the window box assumes one pixel per lane");
+        const bool part = inside[0];
+        int imin = part ? ti[0] : 0x7FFFFFFF, imax = part ? ti[0] : -1;
+        int jmin = part ? tj[0] : 0x7FFFFFFF, jmax = part ? tj[0] : -1;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            imin = min(imin, __shfl_xor(imin, d));
+            imax = max(imax, __shfl_xor(imax, d));
+            jmin = min(jmin, __shfl_xor(jmin, d));
+            jmax = max(jmax, __shfl_xor(jmax, d));
+        }
+        if (imax >= 0) {
+            wx0 = max(imin - 3, 0);
+            wy0 = max(jmin - 3, 0);
+            wrw = min(imax + 3, P.S - 1) - wx0 + 1;
+            const int rh = min(jmax + 3, P.S - 1) - wy0 + 1;
+            win_lds = wrw <= 64 && wrw * rh <= kWinCap;
+            if (win_lds) {
+                for (int r = 0; r < rh; ++r)
+                    if (ln < wrw) win[wv][r * wrw + ln] = lsm[(size_t)(wy0 + r) * (size_t)P.S + (size_t)(wx0 + ln)];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+    }
     // stage 5: features and mask
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const int i = ib + 256 * k;
-        if (i >= w) continue;
+        if (i >= w || j >= h) continue;
         const size_t p = (size_t)j * (size_t)w + (size_t)i;
         float f[C];
 #pragma unroll
@@ -682,7 +718,8 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
 #pragma unroll
                         for (int di = -3; di <= 3; ++di) {
                             const int ii = min(max(ti[k] + di, 0), P.S - 1);
-                            qv[(dj + 3) * 7 + di + 3] = lsm[(size_t)jj * (size_t)P.S + (size_t)ii];
+                            qv[(dj + 3) * 7 + di + 3] = win_lds ? win[wv][(jj - wy0) * wrw + (ii - wx0)]
+                                                                : lsm[(size_t)jj * (size_t)P.S + (size_t)ii];
                         }
                     }
 #pragma unroll
@@ -772,7 +809,8 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
     p.tau = (2.0f * p.tanl) / (float)p.S;
     p.rw = 1.0 / (double)w;
     p.rh = 1.0 / (double)h;
-    dim3 grid((w + 256 * kGatherPx - 1) / (256 * kGatherPx), h);
+    static_assert(kGatherPx == 1, "one pixel per thread");
+    dim3 grid((w + 15) / 16, (h + 15) / 16);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
     if (fs == 1) {
         const size_t n = (size_t)p.S * (size_t)p.S;
