@@ -15,8 +15,9 @@
 //
 // Work distribution (MI355X): one thread per triangle sets up its snapped
 // vertices and the 16x4-texel tiles its bounding box touches; a one-block scan
-// turns tile counts into offsets; then every 64-lane wave rasterises chunks
-// of 64 consecutive (triangle, tile) items, one lane per texel.
+// turns tile counts into offsets; then every 64-lane wave rasterises 64
+// (triangle, tile) items at a time, runs of 4 consecutive items dealt to the
+// waves in turn, one lane per texel.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -37,9 +38,14 @@ constexpr int kTileW = 16, kTileH = 4;
 static_assert(kTileW * kTileH == 64, "one texel per lane of a wave");
 constexpr int kGroup = 32;            // virtual triangles per group of the item -> triangle search
 static_assert(kSetupThreads % kGroup == 0, "a search group must lie inside one setup block");
-// 8192 waves; registers and LDS leave 6 resident per SIMD (6144 on 256 CUs),
-// enough for the ~5300 chunks of a 1080p frame in one round
-constexpr int kRasterBlocks = 2048;
+// Items are dealt to the waves in runs of kRun consecutive items, run r to
+// wave r mod (waves in the grid): a wave's 64 items then sample the whole item
+// list.  Consecutive items belong to one triangle and its neighbouring tiles,
+// and whole runs of them cover nothing (a big triangle's bounding box around
+// its diagonal), so dealing them in large contiguous chunks left some SIMDs
+// with far more covered items to walk than others.
+constexpr int kRun = 4;
+static_assert(64 % kRun == 0, "a wave's 64 items are whole runs");
 constexpr int kStep = 2;              // tile items evaluated together in the walk
 
 __device__ __forceinline__ void to_clip(const Mat4& M, float x, float y, float z, float c[4]) {
@@ -378,11 +384,13 @@ __device__ __forceinline__ void raster_store(const Frag& f, bool k0, bool k1, vo
     }
 }
 
-// Each wave takes chunks of 64 consecutive tile items.  Lane k first finds
-// the triangle and tile of item k of the chunk (64 searches in flight at
-// once), stages that triangle's coefficient record in LDS and tests whether
-// the tile can hold a covered texel (about 40% of bounding-box tiles cannot);
-// the wave then walks the live items, one lane per texel of the tile.
+// Each wave takes 64 tile items at a time (16 runs of kRun consecutive items,
+// strided over the item list; the grid is the number of blocks the device
+// holds at once).  Lane k first finds the triangle and tile of its item (64
+// searches in flight at once), stages that triangle's coefficient record in
+// LDS and tests whether the tile can hold a covered texel (about 40% of
+// bounding-box tiles cannot); the wave then walks the live items, one lane per
+// texel of the tile.
 // Inside the walk nothing waits on vector memory: the depth update is a
 // fire-and-forget integer atomicMin.
 //
@@ -403,7 +411,6 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
     const int lane = threadIdx.x & 63;
     const int nv = P.npass * n_tris;             // virtual triangles
     const long long total = gbase[(nv + kGroup - 1) / kGroup];
-    const long long nchunks = (total + 63) >> 6;
     const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
     const int w0 = P.p[0].w, h0 = P.p[0].h, w1 = P.p[1].w, h1 = P.p[1].h;
     const bool k0 = P.p[0].key64, k1 = P.p[1].key64;
@@ -412,9 +419,11 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
     const int lx = lane % kTileW, ly = lane / kTileW;
     __shared__ TriCoef lcoef[4][64];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (long long chunk = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); chunk < nchunks;
-         chunk += nwaves) {
-        const long long item = (chunk << 6) + lane;
+    const long long wid = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // round q0 of this wave: lane k takes item kRun * (((q0 + k) / kRun) * nwaves + wid) + (q0 + k) % kRun
+    for (long long q0 = 0; (q0 / kRun * nwaves + wid) * kRun < total; q0 += 64) {
+        const long long q = q0 + lane;
+        const long long item = (q / kRun * nwaves + wid) * kRun + q % kRun;
         int v = 0, tx = 0, ty = 0;
         bool live = false;
         if (item < total) {
@@ -440,7 +449,7 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
             }
             live = item < total && tile_live(cl, tx, ty);
         }
-        // the chunk's live items, in order (a wave-uniform lane mask)
+        // the round's live items, in order (a wave-uniform lane mask)
         unsigned long long todo = __ballot(live);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -475,7 +484,7 @@ __global__ void __launch_bounds__(256) k_raster(const TriSetup* __restrict__ set
 #pragma unroll
             for (int u = 0; u < kStep; ++u) raster_store(fr[u], k0, k1, o0, o1);
         }
-        // the slots are rewritten for the next chunk only after every lane is done reading
+        // the slots are rewritten for the next round only after every lane is done reading
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -795,7 +804,15 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     }
     {
         TraceScope ts("raster", sfx, s);
-        k_raster<<<kRasterBlocks, 256, 0, s>>>(setup, coef, gbase, local_off, n_tris, P);
+        // every wave resident at once, so that the dealt items spread evenly over the SIMDs
+        static const int blocks = [] {
+            int dev = 0, cus = 256, per = 1;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_raster, 256, 0) != hipSuccess || per < 1) per = 1;
+            return per * cus;
+        }();
+        k_raster<<<blocks, 256, 0, s>>>(setup, coef, gbase, local_off, n_tris, P);
     }
     return hipGetLastError();
 }
