@@ -79,6 +79,8 @@ struct GatherParams {
     // filled by gather(): per-launch constants of the per-pixel arithmetic
     float tau;                // (2 tanl) / S, float32
     double rw, rh;            // 1 / w and 1 / h, float64, rounded to nearest
+    // the camera's float32 values widened to float64 (exact), once per launch
+    double E_d[3], fwd_d[3], right_d[3], up_d[3], tanx_d, tany_d;
 };
 // Bytes of the linear-depth copy of an S x S shadow map (SOFT8's blocker search).
 size_t linear_map_bytes(int sm_size);

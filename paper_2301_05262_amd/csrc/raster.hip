@@ -233,21 +233,27 @@ __global__ void __launch_bounds__(kSetupThreads) k_tri_setup(const float* __rest
     if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
 }
 
-// Scan of the per-block tile totals written by k_tri_setup into block bases
-// (base[b] = sum of totals of blocks < b, base[nblk] = all tiles); one block,
-// coalesced loads, wave-level scans.
+// Scan of the per-block tile totals written by k_tri_setup into the start of
+// every group of kGroup virtual triangles (gbase[g], gbase[ngroups] = all
+// items); one block, wave-level scans.  A setup block holds two groups: the
+// first starts at the block's base (its local offset is 0), the second at the
+// base plus the local offset of its first triangle, which is loaded together
+// with the block total, so the scan waits on one round of loads.
 __global__ void __launch_bounds__(kScanThreads) k_block_scan(const int* __restrict__ block_sum, int nblk,
-                                                             long long* __restrict__ base,
                                                              const int* __restrict__ local_off, int nv,
                                                              long long* __restrict__ gbase) {
+    static_assert(kSetupThreads == 2 * kGroup, "two search groups per setup block");
     __shared__ long long wsum[kScanThreads / 64];
     __shared__ long long carry;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ngroups = (nv + kGroup - 1) / kGroup;
     if (tid == 0) carry = 0;
     __syncthreads();
     for (int seg = 0; seg < nblk; seg += kScanThreads) {
         const int i = seg + tid;
+        const int t1 = i * kSetupThreads + kGroup;     // first triangle of block i's second group
         const long long v = (i < nblk) ? block_sum[i] : 0;
+        const int lo1 = (i < nblk && t1 < nv) ? local_off[t1] : 0;
         long long incl = v;
         for (int d = 1; d < 64; d <<= 1) {
             const long long u = __shfl_up(incl, d);
@@ -257,19 +263,16 @@ __global__ void __launch_bounds__(kScanThreads) k_block_scan(const int* __restri
         __syncthreads();
         long long woff = carry;
         for (int k = 0; k < wave; ++k) woff += wsum[k];
-        if (i < nblk) base[i] = woff + incl - v;
+        if (i < nblk) {
+            const long long b = woff + incl - v;
+            gbase[2 * i] = b;
+            if (2 * i + 1 < ngroups) gbase[2 * i + 1] = b + lo1;
+        }
         __syncthreads();
         if (tid == kScanThreads - 1) carry = woff + incl;
         __syncthreads();
     }
-    if (tid == 0) base[nblk] = carry;
-    __syncthreads();
-    // first item of every group of kGroup consecutive virtual triangles
-    const int ngroups = (nv + kGroup - 1) / kGroup;
-    for (int g = tid; g <= ngroups; g += kScanThreads) {
-        const int t = g * kGroup;
-        gbase[g] = (t < nv) ? base[t / kSetupThreads] + local_off[t] : carry;
-    }
+    if (tid == 0) gbase[ngroups] = carry;
 }
 
 // The virtual triangle holding tile item `item` (the largest v with
@@ -588,19 +591,19 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
         const double qx0 = ax2 * P.rw, qy0 = ay2 * P.rh;
         const double ndcx = fma(fma(-qx0, (double)w, ax2), P.rw, qx0) - 1.0;
         const double ndcy = fma(fma(-qy0, (double)h, ay2), P.rh, qy0) - 1.0;
-        const double ax = ndcx * (double)P.tanx, ay = ndcy * (double)P.tany;
+        const double ax = ndcx * P.tanx_d, ay = ndcy * P.tany_d;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) D[k][d] = ((double)P.fwd[d] + ax * (double)P.right[d]) + ay * (double)P.up[d];
-        double num = (double)N[k][0] * ((double)V0[k][0] - (double)P.E[0]);
-        num = num + (double)N[k][1] * ((double)V0[k][1] - (double)P.E[1]);
-        num = num + (double)N[k][2] * ((double)V0[k][2] - (double)P.E[2]);
+        for (int d = 0; d < 3; ++d) D[k][d] = (P.fwd_d[d] + ax * P.right_d[d]) + ay * P.up_d[d];
+        double num = (double)N[k][0] * ((double)V0[k][0] - P.E_d[0]);
+        num = num + (double)N[k][1] * ((double)V0[k][1] - P.E_d[1]);
+        num = num + (double)N[k][2] * ((double)V0[k][2] - P.E_d[2]);
         double den = (double)N[k][0] * D[k][0];
         den = den + (double)N[k][1] * D[k][1];
         den = den + (double)N[k][2] * D[k][2];
         if (den == 0.0) fg[k] = false;
         else tt[k] = num / den;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Pw[k][d] = (float)((double)P.E[d] + tt[k] * D[k][d]);
+        for (int d = 0; d < 3; ++d) Pw[k][d] = (float)(P.E_d[d] + tt[k] * D[k][d]);
         to_clip(P.ml, Pw[k][0], Pw[k][1], Pw[k][2], c3[k]);
         inside[k] = fg[k] && c3[k][3] > 1e-6f;
         zf[k] = P.fl;
@@ -763,7 +766,7 @@ size_t raster_workspace_bytes(int n_tris) {
     const size_t nv = 2 * (size_t)n_tris, nblk = (nv + kSetupThreads - 1) / kSetupThreads,
                  ng = (nv + kGroup - 1) / kGroup;
     return align256(nv * sizeof(TriSetup)) + align256(nv * sizeof(TriCoef)) + align256(nv * 4) +
-           align256(nblk * 4) + align256((nblk + 1) * 8) + align256((ng + 1) * 8);
+           align256(nblk * 4) + align256((ng + 1) * 8);
 }
 
 hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws, hipStream_t s) {
@@ -788,8 +791,6 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     wsb += align256((size_t)nv * 4);
     int* block_sum = reinterpret_cast<int*>(wsb);
     wsb += align256((size_t)nblk * 4);
-    long long* base = reinterpret_cast<long long*>(wsb);
-    wsb += align256(((size_t)nblk + 1) * 8);
     long long* gbase = reinterpret_cast<long long*>(wsb);
     {
         TraceScope ts("setup+clear", sfx, s);
@@ -800,7 +801,7 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
     if (n_tris == 0) return hipGetLastError();
     {
         TraceScope ts("tile_scan", sfx, s);
-        k_block_scan<<<1, kScanThreads, 0, s>>>(block_sum, nblk, base, local_off, nv, gbase);
+        k_block_scan<<<1, kScanThreads, 0, s>>>(block_sum, nblk, local_off, nv, gbase);
     }
     {
         TraceScope ts("raster", sfx, s);
@@ -826,6 +827,14 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
     p.tau = (2.0f * p.tanl) / (float)p.S;
     p.rw = 1.0 / (double)w;
     p.rh = 1.0 / (double)h;
+    for (int d = 0; d < 3; ++d) {
+        p.E_d[d] = (double)p.E[d];
+        p.fwd_d[d] = (double)p.fwd[d];
+        p.right_d[d] = (double)p.right[d];
+        p.up_d[d] = (double)p.up[d];
+    }
+    p.tanx_d = (double)p.tanx;
+    p.tany_d = (double)p.tany;
     static_assert(kGatherPx == 1, "one pixel per thread");
     dim3 grid((w + 15) / 16, (h + 15) / 16);
     const auto* g = reinterpret_cast<const unsigned long long*>(gbuf);
