@@ -239,9 +239,21 @@ def training_section(S, torch, seed, steps):
     net.set_weights(torch.from_numpy(S.he_weights(S.U3_SOFT, seed)))
     dw = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
 
+    # the windows' feature builds are independent (one builder, so one
+    # workspace, per window): they run on side streams, a window's frames in
+    # order on one stream, and the forward waits for all of them
+    side = [torch.cuda.Stream() for _ in range(4)]
+    win_of = [k // 4 for k in range(n)]
+
     def step():
+        main = torch.cuda.current_stream()
+        start = main.record_event()
+        for s in side:
+            s.wait_event(start)
         for k, (b, fr) in enumerate(frames):
-            b(fr, soft=True, out=bufs[k])
+            b(fr, soft=True, out=bufs[k], stream=side[win_of[k] % len(side)])
+        for s in side:
+            main.wait_event(s.record_event())
         vis = net.forward_train(feat)
         dvis = (2.0 / vis.numel()) * (vis - target)
         net.backward(feat, dvis, dw_out=dw, saved=True)
