@@ -629,7 +629,7 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
     // stage 4b (SOFT8): when the 7x7 windows of the wave's 8 x 8 pixels fit a
     // small box of the map, the wave stages that box in LDS (one coalesced
     // row per load) and the blocker search reads it from there
-    bool win_lds = false;
+    bool win_lds = false, win_full = false;
     int wx0 = 0, wy0 = 0, wrw = 1;
     __shared__ float win[4][kWinCap];
     if constexpr (SOFT) {
@@ -644,12 +644,20 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
             jmin = min(jmin, __shfl_xor(jmin, d));
             jmax = max(jmax, __shfl_xor(jmax, d));
         }
+        // the same in every lane after the butterfly: scalar from here on
+        imin = __builtin_amdgcn_readfirstlane(imin);
+        imax = __builtin_amdgcn_readfirstlane(imax);
+        jmin = __builtin_amdgcn_readfirstlane(jmin);
+        jmax = __builtin_amdgcn_readfirstlane(jmax);
         if (imax >= 0) {
             wx0 = max(imin - 3, 0);
             wy0 = max(jmin - 3, 0);
             wrw = min(imax + 3, P.S - 1) - wx0 + 1;
             const int rh = min(jmax + 3, P.S - 1) - wy0 + 1;
             win_lds = wrw <= 64 && wrw * rh <= kWinCap;
+            // no window of the wave reaches past the map: every tap is in the
+            // box, unclamped and unmasked
+            win_full = win_lds && imin >= 3 && jmin >= 3 && imax + 3 <= P.S - 1 && jmax + 3 <= P.S - 1;
             if (win_lds) {
                 for (int r = 0; r < rh; ++r)
                     if (ln < wrw) win[wv][r * wrw + ln] = lsm[(size_t)(wy0 + r) * (size_t)P.S + (size_t)(wx0 + ln)];
@@ -721,28 +729,41 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                     const float thr = zf[k] - beta;
                     float sum = 0.0f;
                     int cnt = 0;
-                    // all 49 loads issued together: indices clamped into the map,
-                    // out-of-map taps masked (the same taps, summed in the same order)
-                    float qv[49];
+                    if (win_full) {
+                        // tap (dj, di) is box element (tj + dj - wy0, ti + di - wx0)
+                        const float* wb = &win[wv][(tj[k] - 3 - wy0) * wrw + (ti[k] - 3 - wx0)];
+                        float qv[49];
 #pragma unroll
-                    for (int dj = -3; dj <= 3; ++dj) {
-                        const int jj = min(max(tj[k] + dj, 0), P.S - 1);
+                        for (int dj = 0; dj < 7; ++dj)
 #pragma unroll
-                        for (int di = -3; di <= 3; ++di) {
-                            const int ii = min(max(ti[k] + di, 0), P.S - 1);
-                            qv[(dj + 3) * 7 + di + 3] = win_lds ? win[wv][(jj - wy0) * wrw + (ii - wx0)]
-                                                                : lsm[(size_t)jj * (size_t)P.S + (size_t)ii];
+                            for (int di = 0; di < 7; ++di) qv[dj * 7 + di] = wb[dj * wrw + di];
+#pragma unroll
+                        for (int t = 0; t < 49; ++t)
+                            if (qv[t] < thr) { sum = sum + qv[t]; ++cnt; }
+                    } else {
+                        // all 49 loads issued together: indices clamped into the map,
+                        // out-of-map taps masked (the same taps, summed in the same order)
+                        float qv[49];
+#pragma unroll
+                        for (int dj = -3; dj <= 3; ++dj) {
+                            const int jj = min(max(tj[k] + dj, 0), P.S - 1);
+#pragma unroll
+                            for (int di = -3; di <= 3; ++di) {
+                                const int ii = min(max(ti[k] + di, 0), P.S - 1);
+                                qv[(dj + 3) * 7 + di + 3] = win_lds ? win[wv][(jj - wy0) * wrw + (ii - wx0)]
+                                                                    : lsm[(size_t)jj * (size_t)P.S + (size_t)ii];
+                            }
                         }
-                    }
 #pragma unroll
-                    for (int dj = -3; dj <= 3; ++dj) {
-                        const bool okj = tj[k] + dj >= 0 && tj[k] + dj < P.S;
+                        for (int dj = -3; dj <= 3; ++dj) {
+                            const bool okj = tj[k] + dj >= 0 && tj[k] + dj < P.S;
 #pragma unroll
-                        for (int di = -3; di <= 3; ++di) {
-                            const bool ok = okj && ti[k] + di >= 0 && ti[k] + di < P.S;
-                            // +inf where the map is empty: never below the threshold
-                            const float q = qv[(dj + 3) * 7 + di + 3];
-                            if (ok && q < thr) { sum = sum + q; ++cnt; }
+                            for (int di = -3; di <= 3; ++di) {
+                                const bool ok = okj && ti[k] + di >= 0 && ti[k] + di < P.S;
+                                // +inf where the map is empty: never below the threshold
+                                const float q = qv[(dj + 3) * 7 + di + 3];
+                                if (ok && q < thr) { sum = sum + q; ++cnt; }
+                            }
                         }
                     }
                     if (cnt > 0) zb = sum / (float)cnt;
