@@ -18,12 +18,18 @@ from .api import FeatureBuilder, ShadowNet
 
 
 class BatchedPipeline:
-    def __init__(self, frames, c_in, widths, weights, dtype="bf16", soft=True, device=None):
-        """frames: list of (scene, frame params)."""
+    def __init__(self, frames, c_in, widths, weights, dtype="bf16", soft=True, device=None, side_streams=4):
+        """frames: list of (scene, frame params).  The frames' feature builds
+        (one builder, so one workspace, per frame) are spread over
+        `side_streams` streams forked from the current one and joined before
+        the group's network; in a capture they become parallel branches of
+        the group's graph.  0 builds them in order on the current stream."""
         self.device = torch.device(device if device is not None else "cuda")
         self.soft = soft
         self.frames = frames
         self.builders = [FeatureBuilder(sc, self.device) for sc, _ in frames]
+        with torch.cuda.device(self.device):
+            self.side = [torch.cuda.Stream() for _ in range(side_streams)]
         C = 8 if soft else 6
         groups = OrderedDict()
         for i, (_, fr) in enumerate(frames):
@@ -48,8 +54,19 @@ class BatchedPipeline:
                                 "graph": None, "variants": net.variants()})
 
     def run_group(self, g):
-        for k, i in enumerate(g["idx"]):
-            self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k])
+        if self.side:
+            main = torch.cuda.current_stream(self.device)
+            fork = main.record_event()
+            for s in self.side:
+                s.wait_event(fork)
+            for k, i in enumerate(g["idx"]):
+                s = self.side[k % len(self.side)]
+                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k], stream=s)
+            for s in self.side:
+                main.wait_event(s.record_event())
+        else:
+            for k, i in enumerate(g["idx"]):
+                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k])
         g["net"].forward(g["feat"], vis_out=g["vis"])
 
     def run(self):
