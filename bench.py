@@ -47,12 +47,36 @@ TRAFFIC_MD = os.path.join(ROOT, "profiles", "hbm_traffic_1080p_bf16.md")
 KERNEL_SYMBOL = {
     "raster light+camera": "k_raster",
     "gather hard6": "k_gather<0>",
-    "conv3x3 6+0->16 Pool bf16": "k_conv3x3<bf16, true, 6, 0, 16, Pool, 8>",
-    "conv3x3 16+0->32 Pool bf16": "k_conv3x3<bf16, false, 16, 0, 32, Pool, 8>",
-    "conv3x3 32+0->64 Store bf16": "k_conv3x3<bf16, false, 32, 0, 64, Store, 8>",
-    "conv3x3 32+64->32 Store phase bf16": "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>",
-    "conv3x3 16+32->16 Head phase bf16": "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 4>",
 }
+# BF16 stages in network order: (traced name, kernel with the default tile
+# rows, kernel with the alternative ones); launch variant bit 0 selects the
+# persistent form, bit 1 the alternative rows
+STAGE_SYMBOLS = [
+    ("conv3x3 6+0->16 Pool bf16", "k_conv3x3<bf16, true, 6, 0, 16, Pool, 8>",
+     "k_conv3x3<bf16, true, 6, 0, 16, Pool, 16>"),
+    ("conv3x3 16+0->32 Pool bf16", "k_conv3x3<bf16, false, 16, 0, 32, Pool, 8>",
+     "k_conv3x3<bf16, false, 16, 0, 32, Pool, 16>"),
+    ("conv3x3 32+0->64 Store bf16", "k_conv3x3<bf16, false, 32, 0, 64, Store, 8>",
+     "k_conv3x3<bf16, false, 32, 0, 64, Store, 4>"),
+    ("conv3x3 32+64->32 Store phase bf16", "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>",
+     "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>"),
+    ("conv3x3 16+32->16 Head phase bf16", "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 4>",
+     "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 8>"),
+]
+
+
+def kernel_symbol(name, variants):
+    """Profiled kernel behind a traced BF16 launch, in the launch variants used."""
+    if name in KERNEL_SYMBOL:
+        return KERNEL_SYMBOL[name]
+    for i, (traced, sym, alt) in enumerate(STAGE_SYMBOLS):
+        if traced == name:
+            v = variants[i] if variants and i < len(variants) else 0
+            sym = alt if v & 2 else sym
+            if v & 1:
+                sym = sym.replace("k_conv3x3_up<", "k_conv3x3_up_persist<").replace("k_conv3x3<", "k_conv3x3_persist<")
+            return sym
+    return ""
 
 
 def parse():
@@ -624,7 +648,8 @@ def main():
             roof = {"kernel": dom, "bound": "hbm", "achieved": by / t / 1e9, "peak": HBM_PEAK / 1e9,
                     "unit": "GB/s", "frac": (by / t) / HBM_PEAK}
         from paper_2301_05262_amd.profsum import recorded_traffic
-        measured = recorded_traffic(TRAFFIC_MD).get(KERNEL_SYMBOL.get(dom, ""), None) if head == "bf16" else None
+        measured = (recorded_traffic(TRAFFIC_MD).get(kernel_symbol(dom, results[head]["launch_variants"]), None)
+                    if head == "bf16" else None)
         roof.update({"traffic": measured, "avg_us": kern[dom]["avg_us"], "algorithmic_bytes": by,
                      "algorithmic_flops": fl})
     roof_classes = class_rooflines(results, costs_of, [head] + [f for f in forms if f != head])
