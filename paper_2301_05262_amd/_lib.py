@@ -4,9 +4,16 @@ Argument marshalling only: tensors are passed as raw device pointers and
 every step of the path runs in the library's HIP kernels.  There is no
 fallback: if the library has not been built the import of any entry point
 raises.
+
+With ``NSM_TRACE=1`` in the environment the library's per-kernel timing is
+switched on when it is loaded, and at interpreter exit every kernel's call
+count, median and total time are printed to stderr (the records accumulate
+until then, so use it on bounded runs).
 """
+import atexit
 import ctypes
 import os
+import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libnsm.so")
@@ -101,7 +108,21 @@ def load():
         fn.argtypes = args
         fn.restype = res
     _lib = L
+    if os.environ.get("NSM_TRACE") == "1":
+        _check(L.nsm_trace_enable(1), "nsm_trace_enable")
+        atexit.register(_trace_report)
     return L
+
+
+def _trace_report():
+    """Per-kernel summary of the trace records (NSM_TRACE=1), to stderr."""
+    per = {}
+    for name, ms in nsm_trace_read(1 << 18):
+        per.setdefault(name, []).append(ms)
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        v = sorted(v)
+        print(f"nsm trace: {name}: {len(v)} calls, median {1e3 * v[len(v) // 2]:.2f} us, "
+              f"total {1e3 * sum(v):.1f} us", file=sys.stderr)
 
 
 def _ptr(t):

@@ -4,8 +4,12 @@
 ``nsm_build_features``; ``ShadowNet`` owns a network context and its
 workspace and calls ``nsm_forward`` / ``nsm_backward``; ``NSMForward`` is the
 differentiation form as a ``torch.autograd.Function``.  PyTorch only
-provides device memory and the current stream.
+provides device memory and the current stream.  ``save_checkpoint`` /
+``load_checkpoint`` keep a training run's flat weights and optimizer state.
 """
+import os
+
+import numpy as np
 import torch
 
 from . import _lib
@@ -244,3 +248,20 @@ class TemporalMetric:
         """E = sum / (W H (T - 1)) and the number of contributing pixels."""
         s, k = self.acc.tolist()
         return s / (self.w * self.h * max(self.pairs, 1)), int(k)
+
+
+def save_checkpoint(path, weights, optimizer=None):
+    """Writes the flat float32 weight vector to ``path + ".npy"`` and, if
+    given, the torch optimizer's state to ``path + ".opt.pt"``."""
+    np.save(path + ".npy", weights.detach().to(torch.float32).cpu().numpy())
+    if optimizer is not None:
+        torch.save(optimizer.state_dict(), path + ".opt.pt")
+
+
+def load_checkpoint(path, device=None):
+    """-> (flat float32 weights on `device`, the optimizer state or None).
+    Both files are read without executing anything from them."""
+    w = torch.from_numpy(np.load(path + ".npy", allow_pickle=False)).to(_dev(device))
+    opt = path + ".opt.pt"
+    state = torch.load(opt, map_location=_dev(device), weights_only=True) if os.path.exists(opt) else None
+    return w, state

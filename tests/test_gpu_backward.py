@@ -409,3 +409,42 @@ def test_saved_forward_backward_same_bits():
     other = feat.clone()
     with pytest.raises(nsm.NsmError):
         m.backward(other, dvis, saved=True)
+
+
+def test_resume_from_checkpoint_same_bits(tmp_path):
+    """A training run saved after three Adam steps and resumed in a new
+    network context gives the fourth step's weight gradient and updated
+    weights bit for bit (the backward is deterministic and the checkpoint
+    keeps the flat weights and the optimizer state exactly)."""
+    from paper_2301_05262_amd.api import NSMForward, ShadowNet, load_checkpoint, save_checkpoint
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    feat = torch.from_numpy(_rand((2, 32, 48, 8), 41)).cuda()
+    target = torch.from_numpy(_rand((2, 32, 48), 42, 0.0, 1.0)).cuda()
+
+    def step(net, wts, opt):
+        opt.zero_grad()
+        vis = NSMForward.apply(feat, wts, net)
+        torch.mean((vis - target) ** 2).backward()
+        g = wts.grad.detach().clone()
+        opt.step()
+        return g
+
+    net = ShadowNet(8, S.U3_SOFT.widths, "f32")
+    wts = torch.nn.Parameter(torch.from_numpy(S.he_weights(S.U3_SOFT, 4)).cuda())
+    opt = torch.optim.Adam([wts], lr=3e-3)
+    for _ in range(3):
+        step(net, wts, opt)
+    path = str(tmp_path / "ck")
+    save_checkpoint(path, wts, opt)
+    g_a = step(net, wts, opt)
+    w_a = wts.detach().cpu()
+    w0, state = load_checkpoint(path)
+    net2 = ShadowNet(8, S.U3_SOFT.widths, "f32")
+    wts2 = torch.nn.Parameter(w0)
+    opt2 = torch.optim.Adam([wts2], lr=3e-3)
+    opt2.load_state_dict(state)
+    g_b = step(net2, wts2, opt2)
+    torch.cuda.synchronize()
+    assert torch.equal(g_a.cpu(), g_b.cpu())
+    assert torch.equal(w_a, wts2.detach().cpu())
+

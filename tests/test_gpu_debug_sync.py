@@ -53,3 +53,24 @@ def test_debug_sync_same_bits():
     assert plain.keys() == debug.keys()
     for k in plain:
         assert np.array_equal(plain[k], debug[k]), k
+
+
+def test_trace_env_prints_kernel_summary():
+    """NSM_TRACE=1: a process that runs one 1080p-shaped forward prints, at
+    exit, one summary line per kernel the library launched."""
+    import os
+    import subprocess
+    import sys
+    code = ("import torch, numpy as np, nsm_synth as S\n"
+            "from paper_2301_05262_amd.api import ShadowNet\n"
+            "net = ShadowNet(6, S.U3.widths, 'bf16')\n"
+            "net.set_weights(torch.from_numpy(S.he_weights(S.U3, 0)))\n"
+            "feat = torch.zeros((1, 64, 96, 6), dtype=torch.float32, device='cuda')\n"
+            "net.forward(feat)\n"
+            "torch.cuda.synchronize()\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, NSM_TRACE="1", PYTHONPATH=root + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=180, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("nsm trace: ")]
+    assert any("conv3x3 6+0->16 Pool" in l for l in lines) and len(lines) >= 5, r.stderr[-2000:]
