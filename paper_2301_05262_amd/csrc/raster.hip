@@ -80,11 +80,7 @@ __device__ __forceinline__ void fill2(FillJob a, FillJob b, size_t tid, size_t s
         v.x = v.z = (uint32_t)(f.pattern & 0xFFFFFFFFull);
         v.y = v.w = (uint32_t)(f.pattern >> 32);
         uint4* q = reinterpret_cast<uint4*>(f.p);
-        // streaming stores: the atomics that follow reach these lines from
-        // every XCD and miss L2 either way, so the clear does not allocate there
-        typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-        const u4v vv = {v.x, v.y, v.z, v.w};
-        for (size_t i = tid; i < n16; i += stride) __builtin_nontemporal_store(vv, reinterpret_cast<u4v*>(q) + i);
+        for (size_t i = tid; i < n16; i += stride) q[i] = v;
         // tail (fewer than 16 bytes, 4-byte aligned)
         uint32_t* t32 = reinterpret_cast<uint32_t*>(f.p);
         for (size_t i = n16 * 4 + tid; i < f.bytes / 4; i += stride)
