@@ -89,54 +89,79 @@ __device__ __forceinline__ float up_weight(int Y, int m, int hl) {
 }
 
 // dz_low[q][c] = (sum over the hi-res pixels whose bilinear taps reach q of
-// weight * dup[.][c_off + c]) * (act_low[q][c] > 0).  One thread per low-res
-// pixel and 4 channels: 16-byte loads across channels; the at most 4 x 4
-// reaching hi-res pixels and their weights are found once per thread.
+// weight * dup[.][c_off + c]) * (act_low[q][c] > 0).  One thread per two
+// horizontally adjacent low-res pixels and 4 channels: their 4 x 4 reaching
+// windows share two hi-res columns, so the thread loads a 4 x 6 window once
+// (16-byte loads across channels) and sums each output over its own 4 x 4
+// part in the same order as one pixel alone would.
 __global__ void __launch_bounds__(256) k_up_transpose_mask(const float* __restrict__ dup, int ci_total,
                                                            int c_off, const float* __restrict__ act_low,
                                                            int C, int n, int hl, int wl,
                                                            float* __restrict__ dz_low) {
-    const int C4 = C >> 2;
-    const size_t total = (size_t)n * hl * wl * C4;
+    const int C4 = C >> 2, wp = (wl + 1) >> 1;
+    const size_t total = (size_t)n * hl * wp * C4;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int c = (int)(idx % C4) * 4;
-    const size_t q = idx / C4;
-    const int k = (int)(q % wl);
-    const int m = (int)((q / wl) % hl);
-    const int f = (int)(q / ((size_t)wl * hl));
+    const size_t qp = idx / C4;
+    const int kp = (int)(qp % wp);
+    const int m = (int)((qp / wp) % hl);
+    const int f = (int)(qp / ((size_t)wp * hl));
     const int H = 2 * hl, W = 2 * wl;
-    float wy[4], wx[4];
+    const int k0 = 2 * kp;
+    float wy[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int Y = 2 * m - 1 + t, X = 2 * k - 1 + t;
+        const int Y = 2 * m - 1 + t;
         wy[t] = (Y >= 0 && Y < H) ? up_weight(Y, m, hl) : 0.0f;
-        wx[t] = (X >= 0 && X < W) ? up_weight(X, k, wl) : 0.0f;
     }
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    float wx[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = k0 + u, X = 2 * k - 1 + t;
+            wx[u][t] = (k < wl && X >= 0 && X < W) ? up_weight(X, k, wl) : 0.0f;
+        }
+    float4 s[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
 #pragma unroll
     for (int ty = 0; ty < 4; ++ty) {
         if (wy[ty] == 0.0f) continue;
         const int Y = 2 * m - 1 + ty;
+        float4 d[6];
 #pragma unroll
-        for (int tx = 0; tx < 4; ++tx) {
-            if (wx[tx] == 0.0f) continue;
-            const int X = 2 * k - 1 + tx;
-            const float ww = wy[ty] * wx[tx];
-            const float4 d = *reinterpret_cast<const float4*>(dup + (((size_t)f * H + Y) * W + X) * ci_total + c_off + c);
-            s.x += ww * d.x;
-            s.y += ww * d.y;
-            s.z += ww * d.z;
-            s.w += ww * d.w;
+        for (int col = 0; col < 6; ++col) {
+            const int X = 2 * k0 - 1 + col;
+            const bool need = (col < 4 && wx[0][col] != 0.0f) || (col >= 2 && wx[1][col - 2] != 0.0f);
+            d[col] = need ? *reinterpret_cast<const float4*>(dup + (((size_t)f * H + Y) * W + X) * ci_total + c_off + c)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int tx = 0; tx < 4; ++tx) {
+                if (wx[u][tx] == 0.0f) continue;
+                const float ww = wy[ty] * wx[u][tx];
+                const float4 v = d[2 * u + tx];
+                s[u].x += ww * v.x;
+                s[u].y += ww * v.y;
+                s[u].z += ww * v.z;
+                s[u].w += ww * v.w;
+            }
     }
-    const float4 av = *reinterpret_cast<const float4*>(act_low + q * C + c);
-    float4 o;
-    o.x = av.x > 0.0f ? s.x : 0.0f;
-    o.y = av.y > 0.0f ? s.y : 0.0f;
-    o.z = av.z > 0.0f ? s.z : 0.0f;
-    o.w = av.w > 0.0f ? s.w : 0.0f;
-    *reinterpret_cast<float4*>(dz_low + q * C + c) = o;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int k = k0 + u;
+        if (k >= wl) break;
+        const size_t q = ((size_t)f * hl + m) * wl + k;
+        const float4 av = *reinterpret_cast<const float4*>(act_low + q * C + c);
+        float4 o;
+        o.x = av.x > 0.0f ? s[u].x : 0.0f;
+        o.y = av.y > 0.0f ? s[u].y : 0.0f;
+        o.z = av.z > 0.0f ? s[u].z : 0.0f;
+        o.w = av.w > 0.0f ? s[u].w : 0.0f;
+        *reinterpret_cast<float4*>(dz_low + q * C + c) = o;
+    }
 }
 
 // ---------------------------------------------------------------- pool^T
@@ -464,7 +489,7 @@ size_t head_partial_floats(int c0, size_t npix) { return (size_t)head_grid(npix)
 
 hipError_t up_transpose_mask(int c, int ci_total, int c_off, const float* dup, const float* act_low,
                              int n, int hl, int wl, float* dz_low, hipStream_t s) {
-    const size_t total = (size_t)n * hl * wl * (c / 4);
+    const size_t total = (size_t)n * hl * ((wl + 1) / 2) * (c / 4);
     TraceScope ts("up_transpose_mask", "", s);
     k_up_transpose_mask<<<div_up(total, 256), 256, 0, s>>>(dup, ci_total, c_off, act_low, c, n, hl, wl,
                                                            dz_low);
