@@ -100,7 +100,9 @@ __global__ void __launch_bounds__(256) k_up_transpose_mask(const float* __restri
                                                            float* __restrict__ dz_low) {
     const int C4 = C >> 2, wp = (wl + 1) >> 1;
     const size_t total = (size_t)n * hl * wp * C4;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD b % 8 takes a contiguous run of blocks, so that the hi-res rows
+    // shared by neighbouring low-res rows meet in one L2
+    const size_t idx = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int c = (int)(idx % C4) * 4;
     const size_t qp = idx / C4;
