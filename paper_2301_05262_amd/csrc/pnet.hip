@@ -71,7 +71,7 @@ __device__ __forceinline__ void pconv_tile(const PConvArgs& a, int x0, int y0, i
     constexpr int PS = plane_stride<D>(NPIX);       // block-major LDS planes
     constexpr int RPW = TH / 4, MF = RPW * 2;
     constexpr bool POOL = MODE == PMode::PoolOnly || MODE == PMode::PoolSkip;
-    static_assert(!POOL || RPW == 2, "pooling needs row pairs per wave");
+    static_assert(!POOL || RPW % 2 == 0, "pooling needs whole row pairs per wave");
     static_assert(C1 % 16 == 0, "the 1x1 reads whole 16-channel fragments");
 
     const int h = a.h, w = a.w;
@@ -242,15 +242,18 @@ __device__ __forceinline__ void pconv_tile(const PConvArgs& a, int x0, int y0, i
         if constexpr (POOL) {
             S* pooled = reinterpret_cast<S*>(a.pooled);
             const int hp = h >> 1, wp = w >> 1;
+            // row pair pr of this wave = fragments 4 pr + cf (upper row) and 4 pr + 2 + cf
+#pragma unroll
+            for (int pr = 0; pr < RPW / 2; ++pr)
 #pragma unroll
             for (int cf = 0; cf < 2; ++cf) {
-                const int yp = (y0 >> 1) + wave, xp = ((x0 + cf * 16 + px) >> 1);
+                const int yp = (y0 >> 1) + wave * (RPW / 2) + pr, xp = ((x0 + cf * 16 + px) >> 1);
 #pragma unroll
                 for (int f2 = 0; f2 < NF2; ++f2) {
                     float av[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const float v = acc2[cf][f2][e] + acc2[2 + cf][f2][e];
+                        const float v = acc2[4 * pr + cf][f2][e] + acc2[4 * pr + 2 + cf][f2][e];
                         av[e] = (v + __shfl_xor(v, 1)) * 0.25f;
                     }
                     const int co = f2 * 16 + 4 * g;
@@ -670,7 +673,7 @@ __global__ void k_pack1x1(const float* __restrict__ w, void* __restrict__ out) {
 
 // (cs, cu, sum, c1, c2, mode, float32 input, tile rows, space-to-depth input)
 #define NSM_PSTAGES(X)                                        \
-    X(4, 0, false, 16, 16, PoolOnly, true, 8, false)          \
+    X(4, 0, false, 16, 16, PoolOnly, true, 16, false)         \
     X(16, 0, false, 32, 32, PoolSkip, false, 8, false)        \
     X(16, 0, false, 32, 32, PoolSkip, true, 8, true)          \
     X(32, 0, false, 64, 64, PoolSkip, false, 8, false)        \
