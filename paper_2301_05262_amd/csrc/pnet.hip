@@ -482,12 +482,15 @@ __global__ void __launch_bounds__(kThreads) k_pconv_up0(PConvArgs a, const void*
 // Decoder stages with a summed skip (input = skip + bilinear x2 of the
 // low-resolution tensor) use the same split with two-row tiles (CU > 0,
 // SUM): the low-resolution rows of a one-row tile would not cover its halo.
-template <Dt D, int CS, int CU, bool SUM, int C1, int C2, int TH>
+// With MODE = PoolSkip (two-row tiles) the stage also writes the 2x2 average
+// of its output, one pooled row per tile.
+template <Dt D, int CS, int CU, bool SUM, int C1, int C2, int TH, PMode MODE = PMode::Store>
 __global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
     using T = typename DT<D>::T;
     using S = typename ST<D>::S;
     using G = Geo<D, CS, (SUM ? 0 : CU), C1>;
     static_assert(CU == 0 || (SUM && CU == CS && TH % 2 == 0), "summed decoder stages use even tile rows");
+    static_assert(MODE == PMode::Store || (MODE == PMode::PoolSkip && TH == 2), "pooling takes two-row tiles");
     constexpr int MF = 2 * TH;
     constexpr int EPB = G::EPB, NKG = G::NKG, NF = G::NF, BPT = G::BPT, NB = G::NB;
     constexpr int NFW = NF / 4, NF2 = C2 / 16, N2W = NF2 / 4;
@@ -592,18 +595,37 @@ __global__ void __launch_bounds__(kThreads) k_pconv_cs(PConvArgs a) {
         float bb[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) bb[e] = a.b2[co + e];
+        float val[MF][4];
 #pragma unroll
         for (int m = 0; m < MF; ++m) {
             f32x4 v = red[((0 * MF + m) * NF2 + f2) * 64 + lane];
 #pragma unroll
             for (int wv = 1; wv < 4; ++wv) v += red[((wv * MF + m) * NF2 + f2) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) val[m][e] = fmaxf(v[e] + bb[e], 0.0f);
             const int y = y0 + (m >> 1), x = x0 + (m & 1) * 16 + px;
             if (y < h && x < w) {
-                float v4[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v4[e] = fmaxf(v[e] + bb[e], 0.0f);
                 const size_t p = ((size_t)n * h + y) * w + x;
-                store4<S, C2>(out + p * C2 + co, co, v4);
+                store4<S, C2>(out + p * C2 + co, co, val[m]);
+            }
+        }
+        if constexpr (MODE == PMode::PoolSkip) {
+            // 2x2 average: the tile's two rows, then the neighbouring column (lane ^ 1)
+            S* pooled = reinterpret_cast<S*>(a.pooled);
+            const int hp = h >> 1, wp = w >> 1, yp = y0 >> 1;
+#pragma unroll
+            for (int cf = 0; cf < 2; ++cf) {
+                const int xp = (x0 + cf * 16 + px) >> 1;
+                float av[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = val[cf][e] + val[2 + cf][e];
+                    av[e] = (v + __shfl_xor(v, 1)) * 0.25f;
+                }
+                if ((px & 1) == 0 && yp < hp && xp < wp) {
+                    const size_t p = ((size_t)n * hp + yp) * wp + xp;
+                    store4<S, C2>(pooled + p * C2 + co, co, av);
+                }
             }
         }
     }
@@ -718,6 +740,15 @@ hipError_t plaunch(const PStage& st, const PConvArgs& a, hipStream_t s, bool* fo
         dim3 grid((a.w + kTW - 1) / kTW, (a.h + 1) / 2, a.n);
         TraceScope ts("pconv 128+128->128->64 Store split", pdt_suffix<D>(), s);
         k_pconv_cs<D, 128, 128, true, 128, 64, 2><<<grid, kThreads, 0, s>>>(a);
+        return hipGetLastError();
+    }
+    // and the level-3 encoder (64 -> 128 -> 128, pooled), two rows per block
+    if (st.cs == 64 && st.cu == 0 && !st.sum && st.c1 == 128 && st.c2 == 128 && st.mode == PMode::PoolSkip &&
+        !st.in_f32 && !st.s2d) {
+        *found = true;
+        dim3 grid((a.w + kTW - 1) / kTW, (a.h + 1) / 2, a.n);
+        TraceScope ts("pconv 64+0->128->128 PoolSkip split", pdt_suffix<D>(), s);
+        k_pconv_cs<D, 64, 0, false, 128, 128, 2, PMode::PoolSkip><<<grid, kThreads, 0, s>>>(a);
         return hipGetLastError();
     }
     // the full-resolution stage of up(y_1): phase form where the image has
