@@ -46,30 +46,36 @@ TRAFFIC_MD = os.path.join(ROOT, "profiles", "hbm_traffic_1080p_bf16.md")
 # traced kernel name (BF16 form) -> kernel symbol as the counter summary names it
 KERNEL_SYMBOL = {
     "raster light+camera": "k_raster",
-    "gather hard6": "k_gather<0>",
+    "gather hard6": "k_gather<0, 0>",
+    "gather hard6 stored": "k_gather<0, 1>",
 }
-# BF16 stages in network order: (traced name, kernel with the default tile
-# rows, kernel with the alternative ones); launch variant bit 0 selects the
-# persistent form, bit 1 the alternative rows
+# BF16 stages: (traced name, stage index in network order, kernel with the
+# default tile rows, kernel with the alternative ones); launch variant bit 0
+# selects the persistent form, bit 1 the alternative rows.  The first stage
+# reads float32 features, or (stored) features already in bfloat16.
 STAGE_SYMBOLS = [
-    ("conv3x3 6+0->16 Pool bf16", "k_conv3x3<bf16, true, 6, 0, 16, Pool, 8>",
+    ("conv3x3 6+0->16 Pool bf16", 0, "k_conv3x3<bf16, true, 6, 0, 16, Pool, 8>",
      "k_conv3x3<bf16, true, 6, 0, 16, Pool, 16>"),
-    ("conv3x3 16+0->32 Pool bf16", "k_conv3x3<bf16, false, 16, 0, 32, Pool, 8>",
+    ("conv3x3 6+0->16 Pool stored bf16", 0, "k_conv3x3<bf16, false, 6, 0, 16, Pool, 8>",
+     "k_conv3x3<bf16, false, 6, 0, 16, Pool, 16>"),
+    ("conv3x3 16+0->32 Pool bf16", 1, "k_conv3x3<bf16, false, 16, 0, 32, Pool, 8>",
      "k_conv3x3<bf16, false, 16, 0, 32, Pool, 16>"),
-    ("conv3x3 32+0->64 Store bf16", "k_conv3x3<bf16, false, 32, 0, 64, Store, 8>",
+    ("conv3x3 32+0->64 Store bf16", 2, "k_conv3x3<bf16, false, 32, 0, 64, Store, 8>",
      "k_conv3x3<bf16, false, 32, 0, 64, Store, 4>"),
-    ("conv3x3 32+64->32 Store phase bf16", "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>",
+    ("conv3x3 32+64->32 Store phase bf16", 3, "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>",
      "k_conv3x3_up<bf16, 32, 64, 32, Store, 8, 4>"),
-    ("conv3x3 16+32->16 Head phase bf16", "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 4>",
+    ("conv3x3 16+32->16 Head phase bf16", 4, "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 4>",
      "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 8>"),
 ]
+# forms whose step hands the features over in the network's storage type
+STORED_FORMS = ("bf16", "f16")
 
 
 def kernel_symbol(name, variants):
     """Profiled kernel behind a traced BF16 launch, in the launch variants used."""
     if name in KERNEL_SYMBOL:
         return KERNEL_SYMBOL[name]
-    for i, (traced, sym, alt) in enumerate(STAGE_SYMBOLS):
+    for traced, i, sym, alt in STAGE_SYMBOLS:
         if traced == name:
             v = variants[i] if variants and i < len(variants) else 0
             sym = alt if v & 2 else sym
@@ -116,6 +122,8 @@ def stage_costs(widths, c_in, h, w, dtype):
         out[key] = (flops, in_bytes + out_bytes + wbytes)
 
     add(f"conv3x3 {c_in}+0->{w0} Pool", L0, c_in, 0, w0, L0 * c_in * 4, L0 * w0 * es + L1 * w0 * es)
+    # the same stage on features stored in the storage type, whole 16-byte blocks per pixel
+    add(f"conv3x3 {c_in}+0->{w0} Pool stored", L0, c_in, 0, w0, L0 * 16, L0 * w0 * es + L1 * w0 * es)
     add(f"conv3x3 {w0}+0->{w1} Pool", L1, w0, 0, w1, L1 * w0 * es, L1 * w1 * es + L2 * w1 * es)
     add(f"conv3x3 {w1}+0->{w2} Store", L2, w1, 0, w2, L2 * w1 * es, L2 * w2 * es)
     add(f"conv3x3 {w1}+{w2}->{w1} Store", L1, w1, w2, w1, L1 * w1 * es + L2 * w2 * es, L1 * w1 * es)
@@ -145,9 +153,11 @@ def raster_costs(n_tris, h, w, sm):
 
 def gather_costs(n_tris, h, w, channels, name):
     """Algorithmic HBM bytes of the feature gather: per pixel the 8-byte camera
-    key, the 4-byte map texel, the float32 channels and the mask byte; per
-    triangle its vertices and normal (48 bytes), read once."""
-    return {name: (0.0, float(h * w * (8 + 4 + 4 * channels + 1) + n_tris * 48))}
+    key, the 4-byte map texel, the float32 channels (16 bytes when stored in
+    a 2-byte type) and the mask byte; per triangle its vertices and normal
+    (48 bytes), read once."""
+    return {name: (0.0, float(h * w * (8 + 4 + 4 * channels + 1) + n_tris * 48)),
+            name + " stored": (0.0, float(h * w * (8 + 4 + 16 + 1) + n_tris * 48))}
 
 
 def class_rooflines(results, costs_of, forms):
@@ -190,7 +200,8 @@ def batched_section(S, torch, seed, reps):
     in order.  Per-frame latency is the completion time of the frame's group
     since the batch started.  Beside it: the same graphs with the default
     variants, and one-by-one launches (features + network per frame) in BF16
-    and in FP32."""
+    and in FP32.  BF16 runs take their features in bfloat16
+    (nsm_build_features_stored), FP32 runs in float32."""
     from paper_2301_05262_amd.api import ShadowNet
     from paper_2301_05262_amd.batch import BatchedPipeline
     frames = S.make_batched_frames(seed, 16)
@@ -217,12 +228,15 @@ def batched_section(S, torch, seed, reps):
     for dt in ("bf16", "f32"):
         net = ShadowNet(8, S.U3_SOFT.widths, dt)
         net.set_weights(flat)
+        st = "bf16" if dt == "bf16" else None
         slots = []
         for g in pipe.groups:
             for k, i in enumerate(g["idx"]):
-                slots.append((i, g["bufs"][k], g["feat"][k].unsqueeze(0), torch.empty_like(g["vis"][k:k + 1])))
+                buf = g["bufs"][k] if st else dict(g["bufs"][k], feat=torch.empty(
+                    g["feat"][k].shape, dtype=torch.float32, device=g["feat"].device))
+                slots.append((i, buf, buf["feat"].unsqueeze(0), torch.empty_like(g["vis"][k:k + 1])))
         for i, buf, f, v in slots:                       # warm-up (workspaces)
-            pipe.builders[i](frames[i][1], soft=True, out=buf)
+            pipe.builders[i](frames[i][1], soft=True, out=buf, stored=st)
             net.forward(f, vis_out=v)
         torch.cuda.synchronize()
         frame_ms = []
@@ -230,7 +244,7 @@ def batched_section(S, torch, seed, reps):
             for i, buf, f, v in slots:
                 a, b = ev(), ev()
                 a.record()
-                pipe.builders[i](frames[i][1], soft=True, out=buf)
+                pipe.builders[i](frames[i][1], soft=True, out=buf, stored=st)
                 net.forward(f, vis_out=v)
                 b.record()
                 b.synchronize()
@@ -546,24 +560,26 @@ def main():
     desc = S.U3
     flat = S.he_weights(desc, args.seed)
     fb = FeatureBuilder(scene, dev)
-    buf = fb(fr)
     forms = [f for f in args.forms.split(",") if f]
     nets = {}
     for f in forms:
         nets[f] = ShadowNet(desc.c_in, desc.widths, f, dev)
         nets[f].set_weights(torch.from_numpy(flat))
-    feat = buf["feat"].unsqueeze(0)
+    # BF16 and FP16 steps take the features in the storage type (the gather
+    # rounds them, as the float32 path's first stage would); the others float32
+    bufs = {f: fb(fr, stored=f if f in STORED_FORMS else None) for f in forms}
+    feats = {f: bufs[f]["feat"].unsqueeze(0) for f in forms}
     vis = {f: torch.empty((1, H, W), dtype=torch.float32, device=dev) for f in forms}
     # launch variants timed once for this frame size, as a deployment would at start-up
-    variants = {f: nets[f].autotune(feat) for f in forms}
+    variants = {f: nets[f].autotune(feats[f]) for f in forms}
     torch.cuda.synchronize()
 
     def step(f):
-        fb(fr, out=buf)
-        nets[f].forward(feat, vis_out=vis[f])
+        fb(fr, out=bufs[f], stored=f if f in STORED_FORMS else None)
+        nets[f].forward(feats[f], vis_out=vis[f])
 
     def net_only(f):
-        nets[f].forward(feat, vis_out=vis[f])
+        nets[f].forward(feats[f], vis_out=vis[f])
 
     def timed(fn, f, k):
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -692,6 +708,7 @@ def main():
         "vs_baseline": None, "dtype": head, "data": "synthetic",
         "config": {"workload": WORKLOAD, "width": W, "height": H, "sm_size": fr.sm_size,
                    "n_tris": scene.n_tris, "net": "U-Net 6->16/32/64 (3 levels)", "features": "hard6",
+                   "feature_storage": head if head in STORED_FORMS else "f32",
                    "seed": args.seed, "step": "light z-buffer + camera G-buffer + gather + network"},
         "network_ms": results[head]["network_ms"],
         "forms": results, "roofline": roof, "roofline_classes": roof_classes, "cpu_baseline": cpu,

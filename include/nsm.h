@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define NSM_ABI_VERSION 2
+#define NSM_ABI_VERSION 3
 
 typedef enum {
     NSM_OK = 0,
@@ -181,6 +181,24 @@ nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n
                               float *feat_out, uint8_t *mask_out, void *workspace,
                               size_t ws_bytes, void *stream);
 
+/* nsm_build_features_stored -- the same features written in a network
+ * context's storage type, the input nsm_forward_stored reads (the paper's
+ * network runs in half precision, Sec. 3.5, so its input can be handed over
+ * at half the bytes; a first stage given float32 features rounds them to the
+ * storage type anyway).
+ *   feat_dtype  NSM_BF16 or NSM_F16 (NSM_E_INVALID_ARG otherwise).
+ *   feat_out    [h][w][8] of that type: channel c < C is the float32 feature
+ *               of nsm_build_features rounded to nearest even, channels
+ *               C..7 are zero.  HARD6 and SOFT8 only (NSM_E_UNSUPPORTED for
+ *               PAPER4).
+ * Every other argument, the workspace and the error behaviour are those of
+ * nsm_build_features. */
+nsm_status nsm_build_features_stored(const float *tris, const float *tri_normals, int n_tris,
+                                     const nsm_frame_params *fp, int h, int w, nsm_feature_set fs,
+                                     const uint64_t *gbuf_in, uint64_t *gbuf_out, uint32_t *sm_out,
+                                     nsm_dtype feat_dtype, void *feat_out, uint8_t *mask_out,
+                                     void *workspace, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------- network
  * nsm_create -- a context for one network descriptor and compute dtype.
  * Host only (no device call).  NSM_F32 runs the FP32 network; NSM_BF16 and
@@ -241,6 +259,17 @@ nsm_status nsm_workspace_bytes(const nsm_ctx *ctx, int n, int h, int w, int trai
 nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
                        float *logits_out, void *workspace, size_t ws_bytes, void *stream);
 
+/* nsm_forward_stored -- nsm_forward on features already in the context's
+ * storage type (NSM_BF16 and NSM_F16 contexts of NSM_ARCH_UNET with
+ * c_in 6 or 8; NSM_E_UNSUPPORTED otherwise).
+ *   feat  [n][h][w][8] of the context's dtype, channels past c_in zero
+ *         (the layout of nsm_build_features_stored).
+ * Gives the same bits as nsm_forward on the float32 features that round to
+ * `feat`: the float32 path rounds each feature to nearest even when it
+ * stages the first tile.  Workspace, outputs and errors as nsm_forward. */
+nsm_status nsm_forward_stored(nsm_ctx *ctx, const void *feat, int n, int h, int w, float *vis_out,
+                              float *logits_out, void *workspace, size_t ws_bytes, void *stream);
+
 /* Launch variants of the NSM_ARCH_UNET forward stages (the batched
  * multi-frame pipeline's tuning knob).  Each stage can run as one workgroup
  * per output tile (variant bit 0 clear) or as a persistent grid sized to the
@@ -264,6 +293,12 @@ nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, flo
  * NSM_E_UNSUPPORTED for the paper's architectures. */
 nsm_status nsm_autotune(nsm_ctx *ctx, const float *feat, int n, int h, int w, float *vis_out,
                         void *workspace, size_t ws_bytes, int reps, int *variants_out, void *stream);
+/* nsm_autotune_stored -- nsm_autotune timing the stages as nsm_forward_stored
+ * runs them (feat as for nsm_forward_stored; NSM_E_UNSUPPORTED where that
+ * call is).  The chosen variants serve both forward calls. */
+nsm_status nsm_autotune_stored(nsm_ctx *ctx, const void *feat, int n, int h, int w, float *vis_out,
+                               void *workspace, size_t ws_bytes, int reps, int *variants_out,
+                               void *stream);
 nsm_status nsm_set_stage_variant(nsm_ctx *ctx, int stage, int variant);
 nsm_status nsm_get_stage_variants(const nsm_ctx *ctx, int *variants, int max, int *n_stages);
 

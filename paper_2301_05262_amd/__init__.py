@@ -14,12 +14,14 @@ from ._lib import (  # noqa: F401
     nsm_status_str,
     nsm_features_workspace_bytes,
     nsm_build_features,
+    nsm_build_features_stored,
     nsm_create,
     nsm_destroy,
     nsm_param_count,
     nsm_set_weights,
     nsm_workspace_bytes,
     nsm_forward,
+    nsm_forward_stored,
     nsm_backward,
     nsm_forward_train,
     nsm_backward_saved,
@@ -27,6 +29,7 @@ from ._lib import (  # noqa: F401
     nsm_trace_enable,
     nsm_trace_read,
     nsm_autotune,
+    nsm_autotune_stored,
     nsm_set_stage_variant,
     nsm_get_stage_variants,
     nsm_perturbation_loss_workspace_bytes,

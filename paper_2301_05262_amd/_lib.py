@@ -28,6 +28,7 @@ ARCHS = {"unet": 0, "paper": 1, "paper_s2d": 2}
 
 EXPORTS = [
     "nsm_abi_version", "nsm_status_str", "nsm_features_workspace_bytes", "nsm_build_features",
+    "nsm_build_features_stored", "nsm_forward_stored", "nsm_autotune_stored",
     "nsm_create", "nsm_destroy", "nsm_param_count", "nsm_set_weights", "nsm_workspace_bytes",
     "nsm_forward", "nsm_backward", "nsm_forward_train", "nsm_backward_saved", "nsm_trace_enable", "nsm_trace_read", "nsm_autotune",
     "nsm_set_stage_variant", "nsm_get_stage_variants",
@@ -80,6 +81,10 @@ def load():
         "nsm_features_workspace_bytes": ([i32, i32, i32, i32, psz], i32),
         "nsm_build_features": ([vp, vp, i32, ctypes.POINTER(FrameParams), i32, i32, i32, vp, vp, vp,
                                 vp, vp, vp, sz, vp], i32),
+        "nsm_build_features_stored": ([vp, vp, i32, ctypes.POINTER(FrameParams), i32, i32, i32, vp, vp, vp,
+                                       i32, vp, vp, vp, sz, vp], i32),
+        "nsm_forward_stored": ([vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
+        "nsm_autotune_stored": ([vp, vp, i32, i32, i32, vp, vp, sz, i32, ctypes.POINTER(ctypes.c_int), vp], i32),
         "nsm_create": ([ctypes.POINTER(NetDesc), i32, ctypes.POINTER(vp)], i32),
         "nsm_destroy": ([vp], i32),
         "nsm_param_count": ([vp, psz], i32),
@@ -195,6 +200,18 @@ def nsm_build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_ou
            "nsm_build_features")
 
 
+def nsm_build_features_stored(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_out, sm_out, feat_dtype,
+                              feat_out, mask_out, workspace, ws_bytes, stream=None):
+    if not isinstance(fp, FrameParams):
+        fp = frame_params(fp)
+    fs = FEATURE_SETS.get(fs, fs)
+    _check(load().nsm_build_features_stored(_ptr(tris), _ptr(tri_normals), n_tris, ctypes.byref(fp), h, w,
+                                            fs, _ptr(gbuf_in), _ptr(gbuf_out), _ptr(sm_out),
+                                            DTYPES.get(feat_dtype, feat_dtype), _ptr(feat_out), _ptr(mask_out),
+                                            _ptr(workspace), ws_bytes, _stream(stream)),
+           "nsm_build_features_stored")
+
+
 def nsm_create(c_in, widths, dtype="f32", arch="unet"):
     d = NetDesc()
     d.arch = ARCHS.get(arch, arch)
@@ -233,6 +250,11 @@ def nsm_forward(ctx, feat, n, h, w, vis_out, logits_out, workspace, ws_bytes, st
                               _ptr(workspace), ws_bytes, _stream(stream)), "nsm_forward")
 
 
+def nsm_forward_stored(ctx, feat, n, h, w, vis_out, logits_out, workspace, ws_bytes, stream=None):
+    _check(load().nsm_forward_stored(ctx, _ptr(feat), n, h, w, _ptr(vis_out), _ptr(logits_out),
+                                     _ptr(workspace), ws_bytes, _stream(stream)), "nsm_forward_stored")
+
+
 def nsm_backward(ctx, feat, dvis, n, h, w, dw_out, accumulate, dfeat_out, workspace, ws_bytes,
                  stream=None):
     _check(load().nsm_backward(ctx, _ptr(feat), _ptr(dvis), n, h, w, _ptr(dw_out), int(accumulate),
@@ -258,6 +280,14 @@ def nsm_autotune(ctx, feat, n, h, w, vis_out, workspace, ws_bytes, reps=5, strea
     out = (ctypes.c_int * 16)()
     _check(load().nsm_autotune(ctx, _ptr(feat), n, h, w, _ptr(vis_out), _ptr(workspace), ws_bytes, int(reps),
                                out, _stream(stream)), "nsm_autotune")
+    return nsm_get_stage_variants(ctx)
+
+
+def nsm_autotune_stored(ctx, feat, n, h, w, vis_out, workspace, ws_bytes, reps=5, stream=None):
+    """nsm_autotune on features in the context's storage type."""
+    out = (ctypes.c_int * 16)()
+    _check(load().nsm_autotune_stored(ctx, _ptr(feat), n, h, w, _ptr(vis_out), _ptr(workspace), ws_bytes,
+                                      int(reps), out, _stream(stream)), "nsm_autotune_stored")
     return nsm_get_stage_variants(ctx)
 
 

@@ -58,24 +58,32 @@ class FeatureBuilder:
         self._ws = _grow(self._ws, need, self.device, stream)
         return self._ws
 
-    def __call__(self, fr, soft=False, out=None, stream=None, fs=None):
+    def __call__(self, fr, soft=False, out=None, stream=None, fs=None, stored=None):
         """Returns dict(feat [H,W,C] f32, mask [H,W] u8, sm [S,S] i32 bits, gbuf [H,W] i64 keys).
 
-        fs: 'hard6', 'soft8' or 'paper4' (default: 'soft8' if soft else 'hard6')."""
+        fs: 'hard6', 'soft8' or 'paper4' (default: 'soft8' if soft else 'hard6').
+        stored: None, or 'bf16' / 'f16' for features in a network's storage
+        type, [H,W,8] with the channels past C zero (nsm_build_features_stored)."""
         fs = fs or ("soft8" if soft else "hard6")
         h, w, S = fr.height, fr.width, fr.sm_size
         C = _lib.FEATURE_CHANNELS[fs]
         if out is None:
+            ft = {None: (C, torch.float32), "bf16": (8, torch.bfloat16), "f16": (8, torch.float16)}[stored]
             out = {
-                "feat": torch.empty((h, w, C), dtype=torch.float32, device=self.device),
+                "feat": torch.empty((h, w, ft[0]), dtype=ft[1], device=self.device),
                 "mask": torch.empty((h, w), dtype=torch.uint8, device=self.device),
                 "sm": torch.empty((S, S), dtype=torch.int32, device=self.device),
                 "gbuf": torch.empty((h, w), dtype=torch.int64, device=self.device),
             }
         ws = self.workspace(h, w, S, stream)
-        _lib.nsm_build_features(self.tris, self.normals, self.n_tris, fr, h, w,
-                                fs, None, out["gbuf"], out["sm"],
-                                out["feat"], out["mask"], ws, ws.numel(), stream)
+        if stored is None:
+            _lib.nsm_build_features(self.tris, self.normals, self.n_tris, fr, h, w,
+                                    fs, None, out["gbuf"], out["sm"],
+                                    out["feat"], out["mask"], ws, ws.numel(), stream)
+        else:
+            _lib.nsm_build_features_stored(self.tris, self.normals, self.n_tris, fr, h, w,
+                                           fs, None, out["gbuf"], out["sm"], stored,
+                                           out["feat"], out["mask"], ws, ws.numel(), stream)
         return out
 
 
@@ -112,19 +120,34 @@ class ShadowNet:
         self._ws = _grow(self._ws, need, self.device, stream)
         return self._ws
 
+    _STORED = {"bf16": torch.bfloat16, "f16": torch.float16}
+
+    def _check_feat(self, feat):
+        """True for features in the storage type (nsm_forward_stored), False for float32."""
+        if not feat.is_contiguous():
+            raise ValueError("features must be contiguous")
+        c = feat.shape[-1]
+        if feat.dtype == torch.float32 and c == self.c_in:
+            return False
+        if feat.dtype == self._STORED.get(self.dtype) and c == 8:
+            return True
+        raise ValueError("features must be float32 [N,H,W,c_in], or [N,H,W,8] in the context's storage type")
+
     def forward(self, feat, logits=False, vis_out=None, logits_out=None, stream=None):
+        """Visibility [N,H,W] for float32 features [N,H,W,c_in], or for features
+        [N,H,W,8] in the context's storage type (FeatureBuilder(stored=...))."""
         if feat.dim() == 3:
             feat = feat.unsqueeze(0)
         n, h, w, c = feat.shape
-        if c != self.c_in or feat.dtype != torch.float32 or not feat.is_contiguous():
-            raise ValueError("features must be contiguous float32 [N,H,W,c_in]")
+        stored = self._check_feat(feat)
         vis = vis_out if vis_out is not None else torch.empty((n, h, w), dtype=torch.float32,
                                                               device=feat.device)
         lg = logits_out
         if logits and lg is None:
             lg = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
         ws = self.workspace(n, h, w, stream=stream)
-        _lib.nsm_forward(self.ctx, feat, n, h, w, vis, lg, ws, ws.numel(), stream)
+        call = _lib.nsm_forward_stored if stored else _lib.nsm_forward
+        call(self.ctx, feat, n, h, w, vis, lg, ws, ws.numel(), stream)
         return (vis, lg) if logits else vis
 
     def autotune(self, feat, reps=5, stream=None):
@@ -133,9 +156,10 @@ class ShadowNet:
         if feat.dim() == 3:
             feat = feat.unsqueeze(0)
         n, h, w, _ = feat.shape
+        call = _lib.nsm_autotune_stored if self._check_feat(feat) else _lib.nsm_autotune
         vis = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
         ws = self.workspace(n, h, w, stream=stream)
-        return _lib.nsm_autotune(self.ctx, feat, n, h, w, vis, ws, ws.numel(), reps, stream)
+        return call(self.ctx, feat, n, h, w, vis, ws, ws.numel(), reps, stream)
 
     def set_variant(self, stage, variant):
         _lib.nsm_set_stage_variant(self.ctx, stage, variant)

@@ -1,8 +1,9 @@
 """Batched multi-frame inference captured in HIP graphs.
 
 Frames of mixed sizes are grouped by resolution.  Each group's features are
-built into one [N, H, W, C] tensor (one nsm_build_features call per frame)
-and the network runs once per group: one launch per stage for all frames of
+built into one [N, H, W, C] tensor (one nsm_build_features call per frame;
+for BF16 and FP16 networks nsm_build_features_stored, [N, H, W, 8] in the
+network's storage type) and the network runs once per group: one launch per stage for all frames of
 that size, each stage in the launch variant (one workgroup per tile or a
 persistent grid, default or alternative tile height) that nsm_autotune found
 fastest for the group's shape.  Each group is captured into its own graph;
@@ -18,25 +19,30 @@ from .api import FeatureBuilder, ShadowNet
 
 
 class BatchedPipeline:
-    def __init__(self, frames, c_in, widths, weights, dtype="bf16", soft=True, device=None, side_streams=4):
+    def __init__(self, frames, c_in, widths, weights, dtype="bf16", soft=True, device=None, side_streams=4,
+                 stored=True):
         """frames: list of (scene, frame params).  The frames' feature builds
         (one builder, so one workspace, per frame) are spread over
         `side_streams` streams forked from the current one and joined before
         the group's network; in a capture they become parallel branches of
-        the group's graph.  0 builds them in order on the current stream."""
+        the group's graph.  0 builds them in order on the current stream.
+        stored: hand BF16 / FP16 networks their features in the storage type
+        (same visibility bits, half the feature bytes); float32 otherwise."""
         self.device = torch.device(device if device is not None else "cuda")
         self.soft = soft
+        self.stored = dtype if stored and dtype in ("bf16", "f16") else None
         self.frames = frames
         self.builders = [FeatureBuilder(sc, self.device) for sc, _ in frames]
         with torch.cuda.device(self.device):
             self.side = [torch.cuda.Stream() for _ in range(side_streams)]
-        C = 8 if soft else 6
+        C = 8 if soft or self.stored else 6
+        ft = {None: torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[self.stored]
         groups = OrderedDict()
         for i, (_, fr) in enumerate(frames):
             groups.setdefault((fr.height, fr.width), []).append(i)
         self.groups = []
         for (h, w), idx in groups.items():
-            feat = torch.empty((len(idx), h, w, C), dtype=torch.float32, device=self.device)
+            feat = torch.empty((len(idx), h, w, C), dtype=ft, device=self.device)
             vis = torch.empty((len(idx), h, w), dtype=torch.float32, device=self.device)
             bufs = []
             for k, i in enumerate(idx):
@@ -61,12 +67,13 @@ class BatchedPipeline:
                 s.wait_event(fork)
             for k, i in enumerate(g["idx"]):
                 s = self.side[k % len(self.side)]
-                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k], stream=s)
+                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k], stream=s,
+                                 stored=self.stored)
             for s in self.side:
                 main.wait_event(s.record_event())
         else:
             for k, i in enumerate(g["idx"]):
-                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k])
+                self.builders[i](self.frames[i][1], soft=self.soft, out=g["bufs"][k], stored=self.stored)
         g["net"].forward(g["feat"], vis_out=g["vis"])
 
     def run(self):

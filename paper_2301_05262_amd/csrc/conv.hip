@@ -11,24 +11,32 @@ namespace {
 using namespace ck;
 // ---------------------------------------------------------------- dispatch
 // Supported stages: (cs, cu, co, mode, float32 input, tile rows, alternative
-// tile rows) per dtype.  For decoder stages the tile rows are those of the
-// general kernel's border tiles (the phase-form interior keeps its own);
+// tile rows, trace-name tag) per dtype.  For decoder stages the tile rows
+// are those of the general kernel's border tiles (the phase-form interior
+// keeps its own);
 // 4 rows keep the 16+32 stage's border tile below its phase tile in LDS, so
 // that four blocks fit per CU (the 32+64 stage has no taller border tile:
 // at 8 rows its float32 tile exceeds the LDS).  A launch variant (0..3) picks, bit 0, the
 // persistent grid and, bit 1, the alternative tile rows; every variant
 // computes each output pixel with the same arithmetic in the same order, so
 // all give the same bits (the phase-form interior is the same in all).
+// The first stages also read features already stored in the stage dtype
+// (float32 input false: whole 16-byte blocks per pixel, the channels past
+// the stage's inputs zero), which gives the same bits as the float32 input
+// rounded to that dtype when the tile is staged.
 #define NSM_STAGES(X)                           \
-    X(6, 0, 16, Pool, true, 8, 16)              \
-    X(8, 0, 16, Pool, true, 8, 16)              \
-    X(16, 0, 32, Pool, false, 8, 16)            \
-    X(32, 0, 64, Store, false, 8, 4)            \
-    X(32, 64, 32, Store, false, 4, 4)           \
-    X(16, 32, 16, Head, false, 4, 8)            \
-    X(6, 0, 8, Pool, true, 8, 16)               \
-    X(8, 0, 16, Store, false, 8, 4)             \
-    X(8, 16, 8, Head, false, 8, 4)
+    X(6, 0, 16, Pool, true, 8, 16, "")           \
+    X(8, 0, 16, Pool, true, 8, 16, "")           \
+    X(6, 0, 16, Pool, false, 8, 16, " stored")   \
+    X(8, 0, 16, Pool, false, 8, 16, " stored")   \
+    X(16, 0, 32, Pool, false, 8, 16, "")         \
+    X(32, 0, 64, Store, false, 8, 4, "")         \
+    X(32, 64, 32, Store, false, 4, 4, "")        \
+    X(16, 32, 16, Head, false, 4, 8, "")         \
+    X(6, 0, 8, Pool, true, 8, 16, "")            \
+    X(6, 0, 8, Pool, false, 8, 16, " stored")    \
+    X(8, 0, 16, Store, false, 8, 4, "")          \
+    X(8, 16, 8, Head, false, 8, 4, "")
 
 template <Dt D> constexpr const char* dt_suffix() {
     return D == Dt::F32 ? " f32"
@@ -114,15 +122,15 @@ hipError_t launch_stage(const ConvArgs& a, hipStream_t s, const char* name, bool
 template <Dt D>
 hipError_t launch(const ConvStage& st, OutMode mode, const ConvArgs& a, hipStream_t s, int variant, bool* found) {
     const bool persist = (variant & 1) != 0, alt = (variant & 2) != 0;
-#define NSM_CASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_)                                        \
+#define NSM_CASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, TAG_)                                  \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_ && mode == OutMode::MODE_ &&             \
         a.in_f32 == F32_) {                                                                    \
         *found = true;                                                                         \
         if (alt)                                                                               \
             return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, THA_>(                 \
-                a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_, persist);                 \
+                a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_ TAG_, persist);            \
         return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, TH_>(                      \
-            a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_, persist);                     \
+            a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_ TAG_, persist);                \
     }
     NSM_STAGES(NSM_CASE)
 #undef NSM_CASE
@@ -144,7 +152,7 @@ void pack_stage(const float* w, void* out, hipStream_t s) {
 
 template <Dt D>
 bool pack_dispatch(const ConvStage& st, const float* w, void* out, hipStream_t s, size_t* bytes) {
-#define NSM_PCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_)                                             \
+#define NSM_PCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, TAG_)                                       \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_) {                                        \
         if constexpr (!stage_fits<D, F32_, CS_, CU_>()) return false;                          \
         if (bytes) *bytes = stage_packed_bytes<D, CS_, CU_, CO_>();                            \
@@ -159,7 +167,7 @@ bool pack_dispatch(const ConvStage& st, const float* w, void* out, hipStream_t s
 }  // namespace
 
 bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32) {
-#define NSM_SCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_)                                             \
+#define NSM_SCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, TAG_)                                       \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_ && mode == OutMode::MODE_ && in_f32 == F32_) \
         return dt != Dt::F8M || stage_fits<Dt::F8M, F32_, CS_, CU_>();
     NSM_STAGES(NSM_SCASE)

@@ -385,6 +385,8 @@ struct LowTile {
 // planes: PXS = EPB, BKS = plane stride): channels [0, CS) from `in` ([n][h][w][CS],
 // float32 when IN_F32, zero-padded up to a whole block), channels
 // [CSP, CSP+CU) from the bilinear x2 upsampling of `low` ([n][h/2][w/2][CU]):
+// (an `in` in the stage dtype holds CSP channels per pixel, those past CS
+// zero: a first stage reading features already in the storage type)
 // source row s = (y + 0.5)/2 - 0.5, taps floor(s) (weight 0.25 for even y,
 // 0.75 for odd y) and floor(s) + 1, both clamped to the low-res image; the
 // same along x.  Pixels outside the image are zero (the conv's padding).
@@ -415,8 +417,9 @@ __device__ __forceinline__ void load_halo_tile(typename DT<D>::T* tile, typename
     using S = typename ST<D>::S;
     constexpr int SB = (int)sizeof(S);                              // bytes per stored element
     constexpr int SZ_IN = IN_F32 ? 4 : SB;
-    constexpr int SPX = S2D ? 2 * (CS / 4) * 4 : CS * SZ_IN;          // bytes per pixel step
-    const int srow = S2D ? 2 * (2 * w) * (CS / 4) * 4 : w * CS * SZ_IN;  // bytes per row step
+    constexpr int CST = IN_F32 ? CS : CSP;                          // stored channels per pixel
+    constexpr int SPX = S2D ? 2 * (CS / 4) * 4 : CST * SZ_IN;         // bytes per pixel step
+    const int srow = S2D ? 2 * (2 * w) * (CS / 4) * 4 : w * CST * SZ_IN;  // bytes per row step
     const char* sbase = reinterpret_cast<const char*>(in) + ((long long)n * h + y0 - 1) * srow +
                         (long long)(x0 - 1) * SPX;
     const __amdgpu_buffer_rsrc_t sr = buf_rsrc(sbase);

@@ -85,9 +85,11 @@ struct GatherParams {
 // Bytes of the linear-depth copy of an S x S shadow map (SOFT8's blocker search).
 size_t linear_map_bytes(int sm_size);
 // `lsm` (linear_map_bytes) receives the linear-depth copy of the map first
-// when fs is SOFT8; unused otherwise.
+// when fs is SOFT8; unused otherwise.  od: 0 writes float32 [h][w][C]; 1
+// (bfloat16) and 2 (float16) write [h][w][8] in that type, each channel
+// rounded to nearest even, channels past C zero (HARD6 and SOFT8 only).
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
-                  const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, float* feat,
+                  const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, int od, void* feat,
                   uint8_t* mask, hipStream_t s);
 
 // ------------------------------------------------------ temporal stability

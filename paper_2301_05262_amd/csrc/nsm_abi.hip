@@ -100,11 +100,12 @@ nsm_status nsm_features_workspace_bytes(int n_tris, int h, int w, int sm_size, s
     return NSM_OK;
 }
 
-nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n_tris,
-                              const nsm_frame_params* fp, int h, int w, nsm_feature_set fs,
-                              const uint64_t* gbuf_in, uint64_t* gbuf_out, uint32_t* sm_out,
-                              float* feat_out, uint8_t* mask_out, void* workspace, size_t ws_bytes,
-                              void* stream) {
+// od: 0 float32 features, 1 bfloat16, 2 float16 (gather()).
+static nsm_status build_features(const float* tris, const float* tri_normals, int n_tris,
+                                 const nsm_frame_params* fp, int h, int w, nsm_feature_set fs,
+                                 const uint64_t* gbuf_in, uint64_t* gbuf_out, uint32_t* sm_out, int od,
+                                 void* feat_out, uint8_t* mask_out, void* workspace, size_t ws_bytes,
+                                 void* stream) {
     if (!fp || !sm_out || !feat_out || n_tris < 0) return NSM_E_INVALID_ARG;
     if (n_tris > 0 && (!tris || !tri_normals)) return NSM_E_INVALID_ARG;
     if (fs != NSM_FEAT_HARD6 && fs != NSM_FEAT_SOFT8 && fs != NSM_FEAT_PAPER4) return NSM_E_INVALID_ARG;
@@ -154,11 +155,31 @@ nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n
     gp.tanx = fp->cam_tan_half_x;
     gp.tany = fp->cam_tan_half_y;
     gp.fc = fp->cam_far;
-    if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, lsm_ws, w, h, (int)fs, feat_out,
+    if (gather(tris, tri_normals, n_tris, gp, gb, sm_out, lsm_ws, w, h, (int)fs, od, feat_out,
                mask_out, s) != hipSuccess)
         return NSM_E_LAUNCH;
     if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
     return NSM_OK;
+}
+
+nsm_status nsm_build_features(const float* tris, const float* tri_normals, int n_tris,
+                              const nsm_frame_params* fp, int h, int w, nsm_feature_set fs,
+                              const uint64_t* gbuf_in, uint64_t* gbuf_out, uint32_t* sm_out,
+                              float* feat_out, uint8_t* mask_out, void* workspace, size_t ws_bytes,
+                              void* stream) {
+    return build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_out, sm_out, 0, feat_out,
+                          mask_out, workspace, ws_bytes, stream);
+}
+
+nsm_status nsm_build_features_stored(const float* tris, const float* tri_normals, int n_tris,
+                                     const nsm_frame_params* fp, int h, int w, nsm_feature_set fs,
+                                     const uint64_t* gbuf_in, uint64_t* gbuf_out, uint32_t* sm_out,
+                                     nsm_dtype feat_dtype, void* feat_out, uint8_t* mask_out,
+                                     void* workspace, size_t ws_bytes, void* stream) {
+    if (feat_dtype != NSM_BF16 && feat_dtype != NSM_F16) return NSM_E_INVALID_ARG;
+    if (fs == NSM_FEAT_PAPER4) return NSM_E_UNSUPPORTED;
+    return build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_out, sm_out,
+                          feat_dtype == NSM_BF16 ? 1 : 2, feat_out, mask_out, workspace, ws_bytes, stream);
 }
 
 // ------------------------------------------------------------------ network
@@ -456,8 +477,9 @@ nsm_status check_net_shape(const nsm_ctx* c, int n, int h, int w) {
 // The arguments of every stage of the forward pass; `act_out` (float32
 // [n][h][w][w0]) receives the last decoder activation when non-null
 // (training).
-std::vector<ConvArgs> forward_args(const nsm_ctx* c, const float* feat, int n, int h, int w, float* vis,
-                                   float* logits, char* ws, const FwdLayout& L, float* act_out) {
+std::vector<ConvArgs> forward_args(const nsm_ctx* c, const void* feat, int n, int h, int w, float* vis,
+                                   float* logits, char* ws, const FwdLayout& L, float* act_out,
+                                   bool feat_stored = false) {
     const char* base = reinterpret_cast<const char*>(c->dbuf);
     const float* flat = reinterpret_cast<const float*>(base + c->flat_off);
     const int lv = c->desc.levels;
@@ -470,7 +492,7 @@ std::vector<ConvArgs> forward_args(const nsm_ctx* c, const float* feat, int n, i
         a.n = n;
         a.h = h >> p.level;
         a.w = w >> p.level;
-        a.in_f32 = p.in_f32;
+        a.in_f32 = p.in_f32 && !(feat_stored && out.empty());
         const int l = p.level;
         if (p.mode == OutMode::Pool) {
             a.in = prev;
@@ -498,15 +520,24 @@ std::vector<ConvArgs> forward_args(const nsm_ctx* c, const float* feat, int n, i
 }
 
 // Enqueue the forward pass with the context's launch variants.
-hipError_t run_forward(const nsm_ctx* c, const float* feat, int n, int h, int w, float* vis,
-                       float* logits, char* ws, const FwdLayout& L, float* act_out, hipStream_t s) {
-    const std::vector<ConvArgs> args = forward_args(c, feat, n, h, w, vis, logits, ws, L, act_out);
+hipError_t run_forward(const nsm_ctx* c, const void* feat, int n, int h, int w, float* vis,
+                       float* logits, char* ws, const FwdLayout& L, float* act_out, hipStream_t s,
+                       bool feat_stored = false) {
+    const std::vector<ConvArgs> args = forward_args(c, feat, n, h, w, vis, logits, ws, L, act_out, feat_stored);
     for (size_t i = 0; i < c->stages.size(); ++i) {
         const StagePlan& p = c->stages[i];
         hipError_t e = conv_forward(p.st, c->dt, p.mode, args[i], s, c->variant[i]);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// A context whose first stage can read features stored in its own dtype.
+bool stored_input_ok(const nsm_ctx* c) {
+    if (c->desc.arch != NSM_ARCH_UNET || (c->dt != Dt::BF16 && c->dt != Dt::F16) || c->stages.empty())
+        return false;
+    const StagePlan& p = c->stages[0];
+    return p.in_f32 && (p.st.cs == 6 || p.st.cs == 8) && conv_supported(p.st, c->dt, p.mode, false);
 }
 
 // Training workspace: the float32 forward activations (including the last
@@ -646,10 +677,31 @@ nsm_status nsm_forward(nsm_ctx* ctx, const float* feat, int n, int h, int w, flo
     return NSM_OK;
 }
 
-nsm_status nsm_autotune(nsm_ctx* ctx, const float* feat, int n, int h, int w, float* vis_out, void* workspace,
-                        size_t ws_bytes, int reps, int* variants_out, void* stream) {
+nsm_status nsm_forward_stored(nsm_ctx* ctx, const void* feat, int n, int h, int w, float* vis_out,
+                              float* logits_out, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || !feat || !vis_out) return NSM_E_INVALID_ARG;
+    if (!stored_input_ok(ctx)) return NSM_E_UNSUPPORTED;
+    nsm_status st = check_net_shape(ctx, n, h, w);
+    if (st != NSM_OK) return st;
+    if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
+    const FwdLayout L = plan_forward(ctx, n, h, w, false);
+    if (!workspace || ws_bytes < L.total) return NSM_E_WORKSPACE;
+    if (!device_ok()) return NSM_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ctx->saved.valid = false;
+    debug_sync_begin();
+    if (run_forward(ctx, feat, n, h, w, vis_out, logits_out, reinterpret_cast<char*>(workspace), L, nullptr, s,
+                    true) != hipSuccess)
+        return NSM_E_LAUNCH;
+    if (debug_sync_end(s) != hipSuccess) return NSM_E_LAUNCH;
+    return NSM_OK;
+}
+
+static nsm_status autotune(nsm_ctx* ctx, const void* feat, bool feat_stored, int n, int h, int w, float* vis_out,
+                           void* workspace, size_t ws_bytes, int reps, int* variants_out, void* stream) {
     if (!ctx || !feat || !vis_out || reps < 1 || reps > 1000) return NSM_E_INVALID_ARG;
     if (ctx->desc.arch != NSM_ARCH_UNET) return NSM_E_UNSUPPORTED;
+    if (feat_stored && !stored_input_ok(ctx)) return NSM_E_UNSUPPORTED;
     nsm_status st = check_net_shape(ctx, n, h, w);
     if (st != NSM_OK) return st;
     if (!ctx->has_weights) return NSM_E_NO_WEIGHTS;
@@ -660,8 +712,9 @@ nsm_status nsm_autotune(nsm_ctx* ctx, const float* feat, int n, int h, int w, fl
     ctx->saved.valid = false;
     char* ws = reinterpret_cast<char*>(workspace);
     // one forward with the current variants leaves every stage's input in the workspace
-    if (run_forward(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr, s) != hipSuccess) return NSM_E_LAUNCH;
-    const std::vector<ConvArgs> args = forward_args(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr);
+    if (run_forward(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr, s, feat_stored) != hipSuccess)
+        return NSM_E_LAUNCH;
+    const std::vector<ConvArgs> args = forward_args(ctx, feat, n, h, w, vis_out, nullptr, ws, L, nullptr, feat_stored);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
@@ -700,6 +753,16 @@ nsm_status nsm_autotune(nsm_ctx* ctx, const float* feat, int n, int h, int w, fl
     if (variants_out)
         for (size_t i = 0; i < ctx->stages.size(); ++i) variants_out[i] = ctx->variant[i];
     return NSM_OK;
+}
+
+nsm_status nsm_autotune(nsm_ctx* ctx, const float* feat, int n, int h, int w, float* vis_out, void* workspace,
+                        size_t ws_bytes, int reps, int* variants_out, void* stream) {
+    return autotune(ctx, feat, false, n, h, w, vis_out, workspace, ws_bytes, reps, variants_out, stream);
+}
+
+nsm_status nsm_autotune_stored(nsm_ctx* ctx, const void* feat, int n, int h, int w, float* vis_out,
+                               void* workspace, size_t ws_bytes, int reps, int* variants_out, void* stream) {
+    return autotune(ctx, feat, true, n, h, w, vis_out, workspace, ws_bytes, reps, variants_out, stream);
 }
 
 nsm_status nsm_set_stage_variant(nsm_ctx* ctx, int stage, int variant) {

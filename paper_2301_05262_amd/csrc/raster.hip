@@ -20,6 +20,8 @@
 // waves in turn, one lane per texel.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -535,13 +537,17 @@ __global__ void __launch_bounds__(256) k_linear_map(const uint32_t* __restrict__
 constexpr int kGatherPx = 1;
 constexpr int kWinCap = 1024;     // texels of a wave's staged window box (4 KB of LDS)
 
-template <int FS>
+// OD selects how the channels are written: 0 float32 [h][w][C]; 1 bfloat16
+// and 2 float16 [h][w][8], each float32 channel rounded to nearest even and
+// the channels past C zero (the network's storage type, read by its first
+// stage as whole 16-byte blocks).
+template <int FS, int OD>
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                                                 const float* __restrict__ normals, int n_tris,
                                                 GatherParams P,
                                                 const unsigned long long* __restrict__ gbuf,
                                                 const uint32_t* __restrict__ sm, const float* __restrict__ lsm,
-                                                int w, int h, float* __restrict__ feat,
+                                                int w, int h, void* __restrict__ feat,
                                                 uint8_t* __restrict__ mask) {
     constexpr bool SOFT = FS == 1;
     constexpr int C = FS == 1 ? 8 : (FS == 2 ? 4 : 6);
@@ -772,9 +778,19 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                 f[C - 1] = zb / P.fl;
             }
         }
-        float* o = feat + p * C;
+        if constexpr (OD == 0) {
+            float* o = reinterpret_cast<float*>(feat) + p * C;
 #pragma unroll
-        for (int c = 0; c < C; ++c) o[c] = f[c];
+            for (int c = 0; c < C; ++c) o[c] = f[c];
+        } else {
+            static_assert(C <= 8, "one 16-byte block per pixel");
+            using T = typename std::conditional<OD == 1, __bf16, _Float16>::type;
+            typedef T t8 __attribute__((ext_vector_type(8)));
+            t8 v;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v[c] = c < C ? (T)f[c] : (T)0.0f;
+            reinterpret_cast<t8*>(feat)[p] = v;
+        }
         if (mask) mask[p] = mk;
     }
 }
@@ -842,8 +858,9 @@ hipError_t raster(const float* tris, int n_tris, const RasterPasses& P, void* ws
 size_t linear_map_bytes(int sm_size) { return align256((size_t)sm_size * (size_t)sm_size * 4); }
 
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& params,
-                  const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, float* feat,
+                  const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, int od, void* feat,
                   uint8_t* mask, hipStream_t s) {
+    if (od < 0 || od > 2 || (od != 0 && fs == 2)) return hipErrorInvalidValue;
     GatherParams p = params;
     p.tau = (2.0f * p.tanl) / (float)p.S;
     p.rw = 1.0 / (double)w;
@@ -865,13 +882,25 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
         TraceScope ts("linear_map", "", s);
         k_linear_map<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(sm, n, p.nl, p.fl, lsm);
     }
-    TraceScope ts("gather", fs == 1 ? " soft8" : (fs == 2 ? " paper4" : " hard6"), s);
-    if (fs == 1)
-        k_gather<1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
-    else if (fs == 2)
-        k_gather<2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
-    else
-        k_gather<0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
+    static const char* const names[2][3] = {{" hard6", " soft8", " paper4"}, {" hard6 stored", " soft8 stored", ""}};
+    TraceScope ts("gather", names[od != 0][fs], s);
+    if (fs == 1) {
+        if (od == 1)
+            k_gather<1, 1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
+        else if (od == 2)
+            k_gather<1, 2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
+        else
+            k_gather<1, 0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
+    } else if (fs == 2) {
+        k_gather<2, 0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
+    } else {
+        if (od == 1)
+            k_gather<0, 1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
+        else if (od == 2)
+            k_gather<0, 2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
+        else
+            k_gather<0, 0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
+    }
     return hipGetLastError();
 }
 

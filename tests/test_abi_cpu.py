@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status_strings(lib):
-    assert nsm.nsm_abi_version() == 2
+    assert nsm.nsm_abi_version() == 3
     for s in range(8):
         assert nsm.nsm_status_str(s) != "unknown status"
     assert nsm.nsm_status_str(99) == "unknown status"
@@ -131,6 +131,43 @@ def test_features_validation():
     with pytest.raises(nsm.NsmError) as e:
         nsm.nsm_build_features(**{**args, "fs": 5})
     assert e.value.status == 1
+
+
+def test_stored_feature_calls_validation():
+    import nsm_synth as S
+    sc, fr = S.workload_frame("tiny_64", 0)
+    need = nsm.nsm_features_workspace_bytes(sc.n_tris, 64, 64, 128)
+    args = dict(tris=1024, tri_normals=2048, n_tris=sc.n_tris, fp=_lib.frame_params(fr), h=64, w=64,
+                fs="hard6", gbuf_in=None, gbuf_out=None, sm_out=4096, feat_dtype="bf16", feat_out=8192,
+                mask_out=None, workspace=16384, ws_bytes=need, stream=0)
+    for bad, status in ((dict(feat_dtype="f32"), 1), (dict(feat_dtype="f8"), 1), (dict(fs="paper4"), 3),
+                        (dict(feat_out=None), 1), (dict(ws_bytes=need - 1), 4)):
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_build_features_stored(**{**args, **bad})
+        assert e.value.status == status, bad
+    # stored input: BF16 / FP16 U-Net contexts only (checked before any device call)
+    for c_in, widths, dt, arch in ((6, (16, 32, 64), "f32", "unet"), (6, (16, 32, 64), "f8", "unet"),
+                                   (4, (16, 32, 64, 128, 256), "bf16", "paper")):
+        ctx = nsm.nsm_create(c_in, widths, dt, arch)
+        try:
+            with pytest.raises(nsm.NsmError) as e:
+                nsm.nsm_forward_stored(ctx, 1024, 1, 64, 64, 2048, None, 4096, 1 << 30, 0)
+            assert e.value.status == 3, (dt, arch)
+            with pytest.raises(nsm.NsmError) as e:
+                nsm.nsm_autotune_stored(ctx, 1024, 1, 64, 64, 2048, 4096, 1 << 30, 1, 0)
+            assert e.value.status == 3, (dt, arch)
+        finally:
+            nsm.nsm_destroy(ctx)
+    ctx = nsm.nsm_create(6, (16, 32, 64), "bf16")
+    try:
+        with pytest.raises(nsm.NsmError) as e:      # no weights yet
+            nsm.nsm_forward_stored(ctx, 1024, 1, 64, 64, 2048, None, 4096, 1 << 30, 0)
+        assert e.value.status == 5
+        with pytest.raises(nsm.NsmError) as e:
+            nsm.nsm_forward_stored(ctx, None, 1, 64, 64, 2048, None, 4096, 1 << 30, 0)
+        assert e.value.status == 1
+    finally:
+        nsm.nsm_destroy(ctx)
 
 
 def test_s2d_network_plan():

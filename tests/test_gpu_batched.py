@@ -5,7 +5,10 @@ Every replay (with unrelated eager GPU work and synchronisations between
 replays) must reproduce the eager pass, run before tuning with the default
 variants, bit for bit; features of every frame must equal the oracle's bit
 for bit, and visibility must stay within the BF16 bound of the FP64 oracle.
-The timed replay reports a completion time for every frame.
+The timed replay reports a completion time for every frame.  The pipeline
+hands the BF16 network its features in bfloat16 by default (each channel the
+oracle's float32 feature rounded to nearest even, padding channels zero) and
+in float32 with stored=False; both are checked.
 """
 import numpy as np
 import pytest
@@ -23,15 +26,34 @@ def frames():
     return S.make_batched_frames(5, n_frames=5, sizes=((256, 144), (320, 176)), sm_size=512)
 
 
-def test_graph_replays_match_eager(frames):
+def _bits(t):
+    """Raw bits of a feature tensor (float32, or a 2-byte storage type)."""
+    t = t.cpu()
+    return t.view(torch.int32 if t.dtype == torch.float32 else torch.int16).numpy().copy()
+
+
+def _check_feat(got, ref_feat):
+    """Pipeline features of one frame against the oracle's float32 features."""
+    if got.dtype == torch.float32:
+        np.testing.assert_array_equal(_bits(got), ref_feat.view(np.int32))
+    else:
+        C = ref_feat.shape[-1]
+        want = torch.from_numpy(ref_feat).to(got.dtype).view(torch.int16).numpy()
+        np.testing.assert_array_equal(_bits(got)[..., :C], want)
+        assert not _bits(got)[..., C:].any()
+
+
+@pytest.mark.parametrize("stored", [True, False])
+def test_graph_replays_match_eager(frames, stored):
     from paper_2301_05262_amd.batch import BatchedPipeline
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     flat = S.he_weights(S.U3_SOFT, 9)
-    pipe = BatchedPipeline(frames, 8, S.U3_SOFT.widths, torch.from_numpy(flat), "bf16")
+    pipe = BatchedPipeline(frames, 8, S.U3_SOFT.widths, torch.from_numpy(flat), "bf16", stored=stored)
+    assert pipe.groups[0]["feat"].dtype == (torch.bfloat16 if stored else torch.float32)
     pipe.run()
     torch.cuda.synchronize()
     eager_vis = [v.cpu().numpy().copy() for v in pipe.visibility()]
-    eager_feat = [g["feat"].cpu().numpy().copy() for g in pipe.groups]
+    eager_feat = [_bits(g["feat"]) for g in pipe.groups]
     pipe.capture()
     scratch = torch.zeros(1 << 20, device="cuda")
     for r in range(4):
@@ -49,14 +71,13 @@ def test_graph_replays_match_eager(frames):
         for a, b in zip(eager_vis, pipe.visibility()):
             np.testing.assert_array_equal(a, b.cpu().numpy())
         for a, g in zip(eager_feat, pipe.groups):
-            np.testing.assert_array_equal(a, g["feat"].cpu().numpy())
+            np.testing.assert_array_equal(a, _bits(g["feat"]))
     # oracle parity for every frame
     for g in pipe.groups:
         for k, i in enumerate(g["idx"]):
             sc, fr = frames[i]
             ref = oracle.build_features(sc, fr, soft=True)
-            np.testing.assert_array_equal(g["feat"][k].cpu().numpy().view(np.uint32),
-                                          ref["feat"].view(np.uint32))
+            _check_feat(g["feat"][k], ref["feat"])
             want = onet.forward(8, S.U3_SOFT.widths, flat, ref["feat"][None], keep=False)["vis"][0]
             err = np.abs(g["vis"][k].cpu().numpy() - want).max()
             print(f"[batched frame {i} {fr.width}x{fr.height}] |vis - fp64| {err:.3e}", flush=True)
@@ -68,7 +89,8 @@ def test_benchmark_frames_at_full_size():
     through the captured graph: a 2560 x 1440 frame of an 83,632-triangle
     scene with a soft light, and a 1280 x 720 frame of a 62,512-triangle
     scene with a point light (2048^2 maps).  Features bit-exact against the
-    oracle, BF16 visibility within 2e-2 of the FP64 forward."""
+    oracle (rounded to bfloat16 as the pipeline stores them), BF16 visibility
+    within 2e-2 of the FP64 forward."""
     from paper_2301_05262_amd.batch import BatchedPipeline
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     allf = S.make_batched_frames(0, 16)
@@ -87,7 +109,7 @@ def test_benchmark_frames_at_full_size():
             sc, fr = frames[i]
             print(f"[batched full size] frame {i} {fr.width}x{fr.height} {sc.n_tris} tris", flush=True)
             ref = oracle.build_features(sc, fr, soft=True)
-            np.testing.assert_array_equal(g["feat"][k].cpu().numpy().view(np.uint32), ref["feat"].view(np.uint32))
+            _check_feat(g["feat"][k], ref["feat"])
             want = onet.forward(8, S.U3_SOFT.widths, flat, ref["feat"][None], keep=False)["vis"][0]
             err = np.abs(g["vis"][k].cpu().numpy() - want).max()
             print(f"    |vis - fp64| {err:.3e}", flush=True)
