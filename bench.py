@@ -68,7 +68,7 @@ STAGE_SYMBOLS = [
      "k_conv3x3_up<bf16, 16, 32, 16, Head, 16, 8>"),
 ]
 # forms whose step hands the features over in the network's storage type
-STORED_FORMS = ("bf16", "f16")
+STORED_FORMS = ("bf16", "f16", "f8mfma")
 
 
 def kernel_symbol(name, variants):

@@ -186,11 +186,14 @@ nsm_status nsm_build_features(const float *tris, const float *tri_normals, int n
  * network runs in half precision, Sec. 3.5, so its input can be handed over
  * at half the bytes; a first stage given float32 features rounds them to the
  * storage type anyway).
- *   feat_dtype  NSM_BF16 or NSM_F16 (NSM_E_INVALID_ARG otherwise).
- *   feat_out    [h][w][8] of that type: channel c < C is the float32 feature
- *               of nsm_build_features rounded to nearest even, channels
- *               C..7 are zero.  HARD6 and SOFT8 only (NSM_E_UNSUPPORTED for
- *               PAPER4).
+ *   feat_dtype  NSM_BF16, NSM_F16 or NSM_F8_MFMA (NSM_E_INVALID_ARG
+ *               otherwise).
+ *   feat_out    NSM_BF16 / NSM_F16: [h][w][8] of that type, channel c < C
+ *               the float32 feature of nsm_build_features rounded to
+ *               nearest even, channels C..7 zero.  NSM_F8_MFMA: [h][w][16]
+ *               E4M3 bytes, channel c < C the feature saturated to +-448
+ *               and rounded to nearest even, bytes C..15 zero.  HARD6 and
+ *               SOFT8 only (NSM_E_UNSUPPORTED for PAPER4).
  * Every other argument, the workspace and the error behaviour are those of
  * nsm_build_features. */
 nsm_status nsm_build_features_stored(const float *tris, const float *tri_normals, int n_tris,
@@ -260,13 +263,14 @@ nsm_status nsm_forward(nsm_ctx *ctx, const float *feat, int n, int h, int w, flo
                        float *logits_out, void *workspace, size_t ws_bytes, void *stream);
 
 /* nsm_forward_stored -- nsm_forward on features already in the context's
- * storage type (NSM_BF16 and NSM_F16 contexts of NSM_ARCH_UNET with
- * c_in 6 or 8; NSM_E_UNSUPPORTED otherwise).
- *   feat  [n][h][w][8] of the context's dtype, channels past c_in zero
- *         (the layout of nsm_build_features_stored).
+ * storage type (NSM_BF16, NSM_F16 and NSM_F8_MFMA contexts of
+ * NSM_ARCH_UNET with c_in 6 or 8; NSM_E_UNSUPPORTED otherwise).
+ *   feat  the layout of nsm_build_features_stored for the context's dtype:
+ *         [n][h][w][8] bfloat16 / float16, or [n][h][w][16] E4M3 bytes;
+ *         channels past c_in zero.
  * Gives the same bits as nsm_forward on the float32 features that round to
- * `feat`: the float32 path rounds each feature to nearest even when it
- * stages the first tile.  Workspace, outputs and errors as nsm_forward. */
+ * `feat`: the float32 path rounds each feature the same way when it stages
+ * the first tile.  Workspace, outputs and errors as nsm_forward. */
 nsm_status nsm_forward_stored(nsm_ctx *ctx, const void *feat, int n, int h, int w, float *vis_out,
                               float *logits_out, void *workspace, size_t ws_bytes, void *stream);
 

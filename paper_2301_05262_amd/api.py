@@ -62,13 +62,15 @@ class FeatureBuilder:
         """Returns dict(feat [H,W,C] f32, mask [H,W] u8, sm [S,S] i32 bits, gbuf [H,W] i64 keys).
 
         fs: 'hard6', 'soft8' or 'paper4' (default: 'soft8' if soft else 'hard6').
-        stored: None, or 'bf16' / 'f16' for features in a network's storage
-        type, [H,W,8] with the channels past C zero (nsm_build_features_stored)."""
+        stored: None, or 'bf16' / 'f16' / 'f8mfma' for features in a network's
+        storage type: [H,W,8] bfloat16 / float16 or [H,W,16] E4M3 bytes (uint8),
+        the channels past C zero (nsm_build_features_stored)."""
         fs = fs or ("soft8" if soft else "hard6")
         h, w, S = fr.height, fr.width, fr.sm_size
         C = _lib.FEATURE_CHANNELS[fs]
         if out is None:
-            ft = {None: (C, torch.float32), "bf16": (8, torch.bfloat16), "f16": (8, torch.float16)}[stored]
+            ft = {None: (C, torch.float32), "bf16": (8, torch.bfloat16), "f16": (8, torch.float16),
+                  "f8mfma": (16, torch.uint8)}[stored]
             out = {
                 "feat": torch.empty((h, w, ft[0]), dtype=ft[1], device=self.device),
                 "mask": torch.empty((h, w), dtype=torch.uint8, device=self.device),
@@ -120,7 +122,7 @@ class ShadowNet:
         self._ws = _grow(self._ws, need, self.device, stream)
         return self._ws
 
-    _STORED = {"bf16": torch.bfloat16, "f16": torch.float16}
+    _STORED = {"bf16": (torch.bfloat16, 8), "f16": (torch.float16, 8), "f8mfma": (torch.uint8, 16)}
 
     def _check_feat(self, feat):
         """True for features in the storage type (nsm_forward_stored), False for float32."""
@@ -129,13 +131,14 @@ class ShadowNet:
         c = feat.shape[-1]
         if feat.dtype == torch.float32 and c == self.c_in:
             return False
-        if feat.dtype == self._STORED.get(self.dtype) and c == 8:
+        if (feat.dtype, c) == self._STORED.get(self.dtype):
             return True
-        raise ValueError("features must be float32 [N,H,W,c_in], or [N,H,W,8] in the context's storage type")
+        raise ValueError("features must be float32 [N,H,W,c_in], or in the context's storage type "
+                         "([N,H,W,8] bfloat16 / float16, [N,H,W,16] E4M3 bytes)")
 
     def forward(self, feat, logits=False, vis_out=None, logits_out=None, stream=None):
         """Visibility [N,H,W] for float32 features [N,H,W,c_in], or for features
-        [N,H,W,8] in the context's storage type (FeatureBuilder(stored=...))."""
+        in the context's storage type (FeatureBuilder(stored=...))."""
         if feat.dim() == 3:
             feat = feat.unsqueeze(0)
         n, h, w, c = feat.shape

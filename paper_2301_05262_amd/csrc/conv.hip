@@ -11,7 +11,7 @@ namespace {
 using namespace ck;
 // ---------------------------------------------------------------- dispatch
 // Supported stages: (cs, cu, co, mode, float32 input, tile rows, alternative
-// tile rows, trace-name tag) per dtype.  For decoder stages the tile rows
+// tile rows, features stored in the stage dtype) per dtype.  For decoder stages the tile rows
 // are those of the general kernel's border tiles (the phase-form interior
 // keeps its own);
 // 4 rows keep the 16+32 stage's border tile below its phase tile in LDS, so
@@ -21,22 +21,22 @@ using namespace ck;
 // computes each output pixel with the same arithmetic in the same order, so
 // all give the same bits (the phase-form interior is the same in all).
 // The first stages also read features already stored in the stage dtype
-// (float32 input false: whole 16-byte blocks per pixel, the channels past
-// the stage's inputs zero), which gives the same bits as the float32 input
-// rounded to that dtype when the tile is staged.
+// (stored: whole 16-byte blocks per pixel, the channels past the stage's
+// inputs zero), which gives the same bits as the float32 input rounded to
+// that dtype when the tile is staged; their trace names end in "stored".
 #define NSM_STAGES(X)                           \
-    X(6, 0, 16, Pool, true, 8, 16, "")           \
-    X(8, 0, 16, Pool, true, 8, 16, "")           \
-    X(6, 0, 16, Pool, false, 8, 16, " stored")   \
-    X(8, 0, 16, Pool, false, 8, 16, " stored")   \
-    X(16, 0, 32, Pool, false, 8, 16, "")         \
-    X(32, 0, 64, Store, false, 8, 4, "")         \
-    X(32, 64, 32, Store, false, 4, 4, "")        \
-    X(16, 32, 16, Head, false, 4, 8, "")         \
-    X(6, 0, 8, Pool, true, 8, 16, "")            \
-    X(6, 0, 8, Pool, false, 8, 16, " stored")    \
-    X(8, 0, 16, Store, false, 8, 4, "")          \
-    X(8, 16, 8, Head, false, 8, 4, "")
+    X(6, 0, 16, Pool, true, 8, 16, false)       \
+    X(8, 0, 16, Pool, true, 8, 16, false)       \
+    X(6, 0, 16, Pool, false, 8, 16, true)       \
+    X(8, 0, 16, Pool, false, 8, 16, true)       \
+    X(16, 0, 32, Pool, false, 8, 16, false)     \
+    X(32, 0, 64, Store, false, 8, 4, false)     \
+    X(32, 64, 32, Store, false, 4, 4, false)    \
+    X(16, 32, 16, Head, false, 4, 8, false)     \
+    X(6, 0, 8, Pool, true, 8, 16, false)        \
+    X(6, 0, 8, Pool, false, 8, 16, true)        \
+    X(8, 0, 16, Store, false, 8, 4, false)      \
+    X(8, 16, 8, Head, false, 8, 4, false)
 
 template <Dt D> constexpr const char* dt_suffix() {
     return D == Dt::F32 ? " f32"
@@ -50,10 +50,10 @@ template <Dt D> constexpr const char* phase_suffix() {
 
 // The FP8 compute form packs 16 channels per block: a stage whose stored
 // inputs are not whole blocks of 16 channels has no kernel in it (the
-// float32 network input is padded on load).
-template <Dt D, bool F32, int CS, int CU>
+// float32 network input is padded on load, stored features by the gather).
+template <Dt D, bool F32, int CS, int CU, bool STORED = false>
 constexpr bool stage_fits() {
-    return D != Dt::F8M || ((F32 || CS % 16 == 0) && CU % 16 == 0);
+    return D != Dt::F8M || ((F32 || STORED || CS % 16 == 0) && CU % 16 == 0);
 }
 
 // Tile rows of the phase-form kernel: 16, or 8 for wide stages (96 input
@@ -86,9 +86,9 @@ int resident_blocks(K kernel) {
     return cap;
 }
 
-template <Dt D, bool F32, int CS, int CU, int CO, OutMode MODE, int TH>
+template <Dt D, bool F32, int CS, int CU, int CO, OutMode MODE, int TH, bool STORED = false>
 hipError_t launch_stage(const ConvArgs& a, hipStream_t s, const char* name, bool persist) {
-    if constexpr (!stage_fits<D, F32, CS, CU>()) {
+    if constexpr (!stage_fits<D, F32, CS, CU, STORED>()) {
         return hipErrorInvalidValue;
     } else {
     if constexpr (CU > 0 && !F32 && (MODE == OutMode::Store || MODE == OutMode::Head)) {
@@ -122,15 +122,15 @@ hipError_t launch_stage(const ConvArgs& a, hipStream_t s, const char* name, bool
 template <Dt D>
 hipError_t launch(const ConvStage& st, OutMode mode, const ConvArgs& a, hipStream_t s, int variant, bool* found) {
     const bool persist = (variant & 1) != 0, alt = (variant & 2) != 0;
-#define NSM_CASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, TAG_)                                  \
+#define NSM_CASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, STORED_)                               \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_ && mode == OutMode::MODE_ &&             \
         a.in_f32 == F32_) {                                                                    \
         *found = true;                                                                         \
+        const char* nm = STORED_ ? "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_ " stored"     \
+                                 : "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_;              \
         if (alt)                                                                               \
-            return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, THA_>(                 \
-                a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_ TAG_, persist);            \
-        return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, TH_>(                      \
-            a, s, "conv3x3 " #CS_ "+" #CU_ "->" #CO_ " " #MODE_ TAG_, persist);                \
+            return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, THA_, STORED_>(a, s, nm, persist); \
+        return launch_stage<D, F32_, CS_, CU_, CO_, OutMode::MODE_, TH_, STORED_>(a, s, nm, persist);      \
     }
     NSM_STAGES(NSM_CASE)
 #undef NSM_CASE
@@ -152,7 +152,7 @@ void pack_stage(const float* w, void* out, hipStream_t s) {
 
 template <Dt D>
 bool pack_dispatch(const ConvStage& st, const float* w, void* out, hipStream_t s, size_t* bytes) {
-#define NSM_PCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, TAG_)                                       \
+#define NSM_PCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, STORED_)                                       \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_) {                                        \
         if constexpr (!stage_fits<D, F32_, CS_, CU_>()) return false;                          \
         if (bytes) *bytes = stage_packed_bytes<D, CS_, CU_, CO_>();                            \
@@ -167,9 +167,9 @@ bool pack_dispatch(const ConvStage& st, const float* w, void* out, hipStream_t s
 }  // namespace
 
 bool conv_supported(const ConvStage& st, Dt dt, OutMode mode, bool in_f32) {
-#define NSM_SCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, TAG_)                                       \
+#define NSM_SCASE(CS_, CU_, CO_, MODE_, F32_, TH_, THA_, STORED_)                                       \
     if (st.cs == CS_ && st.cu == CU_ && st.co == CO_ && mode == OutMode::MODE_ && in_f32 == F32_) \
-        return dt != Dt::F8M || stage_fits<Dt::F8M, F32_, CS_, CU_>();
+        return dt != Dt::F8M || stage_fits<Dt::F8M, F32_, CS_, CU_, STORED_>();
     NSM_STAGES(NSM_SCASE)
 #undef NSM_SCASE
     return false;

@@ -87,7 +87,9 @@ size_t linear_map_bytes(int sm_size);
 // `lsm` (linear_map_bytes) receives the linear-depth copy of the map first
 // when fs is SOFT8; unused otherwise.  od: 0 writes float32 [h][w][C]; 1
 // (bfloat16) and 2 (float16) write [h][w][8] in that type, each channel
-// rounded to nearest even, channels past C zero (HARD6 and SOFT8 only).
+// rounded to nearest even, channels past C zero; 3 writes FP8 E4M3 bytes
+// [h][w][16] (saturated to +-448, nearest even), bytes past C zero.  od > 0
+// takes HARD6 or SOFT8.
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& p,
                   const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, int od, void* feat,
                   uint8_t* mask, hipStream_t s);

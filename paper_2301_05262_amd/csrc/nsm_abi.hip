@@ -100,7 +100,7 @@ nsm_status nsm_features_workspace_bytes(int n_tris, int h, int w, int sm_size, s
     return NSM_OK;
 }
 
-// od: 0 float32 features, 1 bfloat16, 2 float16 (gather()).
+// od: 0 float32 features, 1 bfloat16, 2 float16, 3 FP8 E4M3 (gather()).
 static nsm_status build_features(const float* tris, const float* tri_normals, int n_tris,
                                  const nsm_frame_params* fp, int h, int w, nsm_feature_set fs,
                                  const uint64_t* gbuf_in, uint64_t* gbuf_out, uint32_t* sm_out, int od,
@@ -176,10 +176,11 @@ nsm_status nsm_build_features_stored(const float* tris, const float* tri_normals
                                      const uint64_t* gbuf_in, uint64_t* gbuf_out, uint32_t* sm_out,
                                      nsm_dtype feat_dtype, void* feat_out, uint8_t* mask_out,
                                      void* workspace, size_t ws_bytes, void* stream) {
-    if (feat_dtype != NSM_BF16 && feat_dtype != NSM_F16) return NSM_E_INVALID_ARG;
+    if (feat_dtype != NSM_BF16 && feat_dtype != NSM_F16 && feat_dtype != NSM_F8_MFMA) return NSM_E_INVALID_ARG;
     if (fs == NSM_FEAT_PAPER4) return NSM_E_UNSUPPORTED;
-    return build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_out, sm_out,
-                          feat_dtype == NSM_BF16 ? 1 : 2, feat_out, mask_out, workspace, ws_bytes, stream);
+    const int od = feat_dtype == NSM_BF16 ? 1 : (feat_dtype == NSM_F16 ? 2 : 3);
+    return build_features(tris, tri_normals, n_tris, fp, h, w, fs, gbuf_in, gbuf_out, sm_out, od, feat_out,
+                          mask_out, workspace, ws_bytes, stream);
 }
 
 // ------------------------------------------------------------------ network
@@ -534,7 +535,8 @@ hipError_t run_forward(const nsm_ctx* c, const void* feat, int n, int h, int w, 
 
 // A context whose first stage can read features stored in its own dtype.
 bool stored_input_ok(const nsm_ctx* c) {
-    if (c->desc.arch != NSM_ARCH_UNET || (c->dt != Dt::BF16 && c->dt != Dt::F16) || c->stages.empty())
+    if (c->desc.arch != NSM_ARCH_UNET || (c->dt != Dt::BF16 && c->dt != Dt::F16 && c->dt != Dt::F8M) ||
+        c->stages.empty())
         return false;
     const StagePlan& p = c->stages[0];
     return p.in_f32 && (p.st.cs == 6 || p.st.cs == 8) && conv_supported(p.st, c->dt, p.mode, false);

@@ -540,7 +540,9 @@ constexpr int kWinCap = 1024;     // texels of a wave's staged window box (4 KB 
 // OD selects how the channels are written: 0 float32 [h][w][C]; 1 bfloat16
 // and 2 float16 [h][w][8], each float32 channel rounded to nearest even and
 // the channels past C zero (the network's storage type, read by its first
-// stage as whole 16-byte blocks).
+// stage as whole 16-byte blocks); 3 FP8 E4M3 bytes [h][w][16], each channel
+// saturated to +-448 and rounded to nearest even by the hardware
+// conversion, the bytes past C zero.
 template <int FS, int OD>
 __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
                                                 const float* __restrict__ normals, int n_tris,
@@ -782,6 +784,21 @@ __global__ void __launch_bounds__(256) k_gather(const float* __restrict__ tris,
             float* o = reinterpret_cast<float*>(feat) + p * C;
 #pragma unroll
             for (int c = 0; c < C; ++c) o[c] = f[c];
+        } else if constexpr (OD == 3) {
+            static_assert(C <= 8, "one 16-byte block per pixel");
+            float c8[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) c8[c] = c < C ? __builtin_amdgcn_fmed3f(f[c], 448.0f, -448.0f) : 0.0f;
+            uint4 v;
+            int lo = __builtin_amdgcn_cvt_pk_fp8_f32(c8[0], c8[1], 0, false);
+            lo = __builtin_amdgcn_cvt_pk_fp8_f32(c8[2], c8[3], lo, true);
+            int hi = __builtin_amdgcn_cvt_pk_fp8_f32(c8[4], c8[5], 0, false);
+            hi = __builtin_amdgcn_cvt_pk_fp8_f32(c8[6], c8[7], hi, true);
+            v.x = (unsigned)lo;
+            v.y = (unsigned)hi;
+            v.z = 0u;
+            v.w = 0u;
+            reinterpret_cast<uint4*>(feat)[p] = v;
         } else {
             static_assert(C <= 8, "one 16-byte block per pixel");
             using T = typename std::conditional<OD == 1, __bf16, _Float16>::type;
@@ -860,7 +877,7 @@ size_t linear_map_bytes(int sm_size) { return align256((size_t)sm_size * (size_t
 hipError_t gather(const float* tris, const float* normals, int n_tris, const GatherParams& params,
                   const uint64_t* gbuf, const uint32_t* sm, float* lsm, int w, int h, int fs, int od, void* feat,
                   uint8_t* mask, hipStream_t s) {
-    if (od < 0 || od > 2 || (od != 0 && fs == 2)) return hipErrorInvalidValue;
+    if (od < 0 || od > 3 || (od != 0 && fs == 2)) return hipErrorInvalidValue;
     GatherParams p = params;
     p.tau = (2.0f * p.tanl) / (float)p.S;
     p.rw = 1.0 / (double)w;
@@ -889,6 +906,8 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
             k_gather<1, 1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
         else if (od == 2)
             k_gather<1, 2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
+        else if (od == 3)
+            k_gather<1, 3><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
         else
             k_gather<1, 0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, lsm, w, h, feat, mask);
     } else if (fs == 2) {
@@ -898,6 +917,8 @@ hipError_t gather(const float* tris, const float* normals, int n_tris, const Gat
             k_gather<0, 1><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
         else if (od == 2)
             k_gather<0, 2><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
+        else if (od == 3)
+            k_gather<0, 3><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
         else
             k_gather<0, 0><<<grid, 256, 0, s>>>(tris, normals, n_tris, p, g, sm, nullptr, w, h, feat, mask);
     }

@@ -1,13 +1,15 @@
 """Features handed to the network in its storage type.
 
 nsm_build_features_stored writes each feature channel rounded to bfloat16 or
-float16 (nearest even) in [H][W][8] with the channels past C zero;
-nsm_forward_stored reads that layout directly.  Checked here:
+float16 (nearest even) in [H][W][8], or to FP8 E4M3 bytes in [H][W][16], with
+the channels past C zero; nsm_forward_stored reads that layout directly.
+Checked here:
 
 * the stored features equal the oracle's float32 features (bit-exact with
-  the GPU's, tested elsewhere) rounded on the CPU by torch, channel by
-  channel, and the padding channels are zero; G-buffer, shadow map and mask
-  are those of nsm_build_features;
+  the GPU's, tested elsewhere) rounded on the CPU: by torch for bfloat16 and
+  float16, by the oracle's E4M3 rounding for the FP8 form; the padding
+  channels are zero; G-buffer, shadow map and mask are those of
+  nsm_build_features;
 * the network on stored features gives the same bits as on the float32
   features (the float32 path rounds when it stages its first tile), in every
   launch variant of the first stage and after nsm_autotune_stored, and its
@@ -24,7 +26,8 @@ from oracle import net as onet
 
 pytestmark = pytest.mark.gpu
 
-TORCH_DT = {"bf16": torch.bfloat16, "f16": torch.float16}
+TORCH_DT = {"bf16": torch.bfloat16, "f16": torch.float16, "f8mfma": torch.uint8}
+WIDTH = {"bf16": 8, "f16": 8, "f8mfma": 16}
 
 
 def _builder(scene):
@@ -58,7 +61,7 @@ FRAMES = list(_frames())
 
 
 @pytest.mark.parametrize("case", range(len(FRAMES)))
-@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("dt", ["bf16", "f16", "f8mfma"])
 def test_stored_features_are_rounded_oracle_features(case, dt):
     name, sc, fr, soft = FRAMES[case]
     fb = _builder(sc)
@@ -67,19 +70,28 @@ def test_stored_features_are_rounded_oracle_features(case, dt):
     got = fb(fr, soft=soft, stored=dt)
     plain = fb(fr, soft=soft)
     torch.cuda.synchronize()
-    assert got["feat"].dtype == TORCH_DT[dt] and tuple(got["feat"].shape) == (fr.height, fr.width, 8)
-    want = torch.from_numpy(ref["feat"]).to(TORCH_DT[dt])
+    assert got["feat"].dtype == TORCH_DT[dt] and tuple(got["feat"].shape) == (fr.height, fr.width, WIDTH[dt])
     gf = got["feat"].cpu()
-    n_bad = int((_bits(gf[..., :C]) != _bits(want)).sum())
-    print(f"[{name} {dt}] stored feature mismatches {n_bad} of {want.numel()}", flush=True)
+    if dt == "f8mfma":
+        # E4M3 bytes decoded exactly (no byte is the NaN pattern: the kernel saturates)
+        vals = gf[..., :C].view(torch.float8_e4m3fn).to(torch.float64).numpy()
+        want = onet._round_e4m3_via_f32(ref["feat"])
+        n_bad = int((vals != want).sum())
+        pad = gf[..., C:].numpy()
+    else:
+        want = torch.from_numpy(ref["feat"]).to(TORCH_DT[dt])
+        n_bad = int((_bits(gf[..., :C]) != _bits(want)).sum())
+        pad = _bits(gf[..., C:])
+    print(f"[{name} {dt}] stored feature mismatches {n_bad} of {ref['feat'].size}", flush=True)
     assert n_bad == 0
-    assert int((_bits(gf[..., C:]) != 0).sum()) == 0
+    assert int((pad != 0).sum()) == 0
     for k in ("gbuf", "sm", "mask"):
         assert torch.equal(got[k], plain[k]), k
 
 
 @pytest.mark.parametrize("desc,name,dt", [(S.U3, "hard_1080p", "bf16"), (S.U3, "hard_1080p", "f16"),
-                                          (S.U2, "tiny_64", "bf16"), (S.U3_SOFT, "soft", "bf16")])
+                                          (S.U3, "hard_1080p", "f8mfma"), (S.U2, "tiny_64", "bf16"),
+                                          (S.U3_SOFT, "soft", "bf16"), (S.U3_SOFT, "soft", "f8mfma")])
 def test_forward_on_stored_features_same_bits(desc, name, dt):
     if name == "soft":
         sc = S.make_scene("objects60", 3)
