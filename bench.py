@@ -27,6 +27,7 @@ import argparse
 import json
 import os
 import sys
+import gc
 import time
 
 import numpy as np
@@ -582,14 +583,30 @@ def main():
         nets[f].forward(feats[f], vis_out=vis[f])
 
     def timed(fn, f, k):
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        s.record()
-        for _ in range(k):
-            fn(f)
-        e.record()
-        torch.cuda.synchronize()
+        # the host only enqueues here; a garbage-collector pass over this
+        # process's heap in the middle of the loop could leave the GPU idle
+        gc.collect()
+        gc.disable()
+        try:
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            s.record()
+            for _ in range(k):
+                fn(f)
+            e.record()
+            torch.cuda.synchronize()
+        finally:
+            gc.enable()
         return s.elapsed_time(e) / k
+
+    # Sustained load first: the autotune's short synchronised launches leave
+    # the GPU below its steady-state clocks, which the first timed form would
+    # otherwise absorb.  A renderer runs frames back to back.
+    t_end = time.perf_counter() + 0.5
+    while time.perf_counter() < t_end:
+        for _ in range(50):
+            step(forms[0])
+        torch.cuda.synchronize()
 
     results = {}
     for f in forms:

@@ -68,9 +68,12 @@ class FeatureBuilder:
         fs = fs or ("soft8" if soft else "hard6")
         h, w, S = fr.height, fr.width, fr.sm_size
         C = _lib.FEATURE_CHANNELS[fs]
+        ft = {None: (C, torch.float32), "bf16": (8, torch.bfloat16), "f16": (8, torch.float16),
+              "f8mfma": (16, torch.uint8)}[stored]
+        if out is not None and (tuple(out["feat"].shape) != (h, w, ft[0]) or out["feat"].dtype != ft[1]
+                                or not out["feat"].is_contiguous()):
+            raise ValueError(f"out['feat'] must be a contiguous {ft[1]} tensor of shape {(h, w, ft[0])}")
         if out is None:
-            ft = {None: (C, torch.float32), "bf16": (8, torch.bfloat16), "f16": (8, torch.float16),
-                  "f8mfma": (16, torch.uint8)}[stored]
             out = {
                 "feat": torch.empty((h, w, ft[0]), dtype=ft[1], device=self.device),
                 "mask": torch.empty((h, w), dtype=torch.uint8, device=self.device),

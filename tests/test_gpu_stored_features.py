@@ -147,3 +147,12 @@ def test_stored_calls_refuse_unsupported():
     mb = ShadowNet(S.U2.c_in, S.U2.widths, "bf16")
     with pytest.raises(ValueError):
         mb.forward(torch.zeros((1, 64, 64, 8), dtype=torch.float16, device="cuda"))
+    # a caller's buffer of another type or shape is refused before any launch
+    plain = fb(fr)
+    with pytest.raises(ValueError):
+        fb(fr, out=plain, stored="bf16")
+    st = fb(fr, stored="f8mfma")
+    with pytest.raises(ValueError):
+        fb(fr, out=st, stored="bf16")
+    with pytest.raises(ValueError):
+        fb(fr, out=st)
