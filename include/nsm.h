@@ -208,7 +208,8 @@ nsm_status nsm_build_features_stored(const float *tris, const float *tri_normals
  * NSM_F16 run the precision form (activations and 3x3 weights stored in
  * that type, MFMA products accumulated in float32; the paper quantises its
  * network to half precision, Sec. 3.5).  Inputs and outputs of every call
- * stay float32.  Decoder stages fold the bilinear x2 upsampling into their
+ * stay float32, except the features nsm_forward_stored takes in the storage
+ * type.  Decoder stages fold the bilinear x2 upsampling into their
  * weights away from the image border (four phase kernels per stage, formed
  * in float64 and rounded once to the storage type), so the upsampled tensor
  * is never rounded to the storage type there.
